@@ -1,0 +1,160 @@
+/*
+ * dmrg.h - C ABI of the MI355X two-site shell-model DMRG hot path.
+ *
+ * Method (Legeza, Veis, Poves, Dukelsky, arXiv:1507.00161):
+ *   H = sum_a eps_a c+_a c_a + two-body term            (Eq. 1)
+ * on m-scheme single-particle sites a = (n, l, j, m, tau_z), each empty or
+ * occupied (the C^2 representation, local dimension 2).  The state is
+ * optimised on a two-site superblock  Xi(l) x Lambda x Lambda x Xi(r)  of an
+ * ordered orbital chain, the block bases are truncated to D states through
+ * the Schmidt (SVD) decomposition of the superblock state, and the chain is
+ * swept back and forth (the two-site DMRG paragraph and the block-state
+ * paragraph that introduces M, called D here).  The conserved quantities are
+ * the proton and neutron numbers and the total J_z (the m-scheme basis
+ * dimension "for J_z = 0").
+ *
+ * This library runs one GPU (gfx950).  All device work is issued on the
+ * context stream; calls on one context must not overlap (one host thread at
+ * a time per context); different contexts are independent.  Nothing throws or
+ * aborts across this boundary: every call returns a dmrg_status and stores a
+ * message retrievable with dmrg_last_error.
+ */
+#ifndef DMRG_MI355X_H
+#define DMRG_MI355X_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum dmrg_status {
+    DMRG_OK = 0,
+    DMRG_WARN_NOT_CONVERGED = 1,   /* a Davidson solve hit davidson_max_iter; results valid */
+    DMRG_ERR_ARG = -1,             /* invalid argument (null pointer, D < 1, bad ordering, ...) */
+    DMRG_ERR_HAMILTONIAN = -2,     /* eps / V violate a symmetry or selection rule */
+    DMRG_ERR_TARGET = -3,          /* (n_p, n_n, 2M) not reachable in the space */
+    DMRG_ERR_STATE = -4,           /* call out of order (e.g. apply before any sweep) */
+    DMRG_ERR_OUT_OF_MEMORY = -5,   /* device allocation failed or mem_cap_bytes exceeded */
+    DMRG_ERR_DEVICE = -6           /* HIP / library error */
+} dmrg_status;
+
+typedef enum dmrg_precision {
+    DMRG_FP64 = 0,        /* every H_eff.psi sector GEMM in FP64 */
+    DMRG_MIXED_FP32 = 1,  /* Davidson expansion products in FP32, FP64 residual correction */
+    DMRG_MIXED_BF16 = 2   /* BF16 inputs with FP32 accumulation, FP64 residual correction */
+} dmrg_precision;
+
+typedef struct dmrg_options {
+    int32_t precision;             /* dmrg_precision, default DMRG_FP64 */
+    uint64_t seed;                 /* key of the hash-random start, default 1507 */
+    double davidson_tol;           /* residual 2-norm (MeV) for convergence, default 1e-7 */
+    int32_t davidson_max_iter;     /* H_eff products per solve, default 100 */
+    int32_t davidson_max_subspace; /* subspace size before restart, default 24 (<= 32) */
+    double noise;                  /* density-matrix perturbation weight, default 0 */
+    int32_t noise_sweeps;          /* sweeps (from the start) that use `noise`, default 0 */
+    int32_t select_basis;          /* 1: truncate by determinant selection (test mode) */
+    double tie_tol;                /* truncation tie tolerance on weights, default 1e-13 */
+    int32_t device;                /* HIP device ordinal, default 0 */
+    void* stream;                  /* hipStream_t to use, NULL = context-owned stream */
+    uint64_t mem_cap_bytes;        /* 0 = no cap; else device bytes the context may hold */
+    uint64_t scratch_bytes;        /* 0 = automatic; else cap on H_eff intermediate buffers */
+} dmrg_options;
+
+typedef struct dmrg_sweep_stats {
+    double energy;            /* lowest step energy of the sweep (MeV) */
+    double last_theta;        /* energy at the last step */
+    double discarded_max;     /* largest discarded weight 1 - sum(kept) */
+    double discarded_sum;
+    int64_t products_low;     /* H_eff.psi products in reduced precision */
+    int64_t products_fp64;    /* H_eff.psi products in FP64 */
+    int64_t solves;           /* Davidson solves */
+    int64_t not_converged;    /* solves that hit davidson_max_iter */
+    double heff_flops;        /* algorithmic flops of all H_eff.psi products */
+    double heff_seconds;      /* device time of all H_eff.psi products (HIP events) */
+    double sweep_seconds;     /* wall time of the sweep */
+    double renorm_seconds;    /* wall time in truncation + renormalisation + prediction */
+    double blocking_seconds;  /* wall time building enlarged-block operators and plans */
+    int32_t status;           /* per-context status (dmrg_sweep_many) */
+    int32_t steps;            /* two-site steps done */
+} dmrg_sweep_stats;
+
+typedef struct dmrg_ctx dmrg_ctx;
+
+/* Fill `opt` with the defaults listed above. */
+void dmrg_default_options(dmrg_options* opt);
+
+/* Create a context on opt->device (NULL opt = defaults).  *out owns all its
+ * device memory; release with dmrg_destroy.  Errors: ARG, DEVICE. */
+dmrg_status dmrg_create(const dmrg_options* opt, dmrg_ctx** out);
+void dmrg_destroy(dmrg_ctx* ctx);
+
+/* Hamiltonian of Eq. 1 on n_sites m-scheme sites, written
+ *   H = sum_i eps_i n_i + 1/4 sum_ijkl V_ijkl c+_i c+_j c_l c_k
+ * (host arrays, copied; the caller keeps ownership):
+ *   species[n]  0 = proton, 1 = neutron;  two_m[n]  twice the m projection;
+ *   eps[n] MeV; V[n*n*n*n] row-major V[((i*n+j)*n+k)*n+l], antisymmetrised.
+ * Validation (tolerance 1e-12 * max|V|): V_ijkl = -V_jikl = -V_ijlk = V_klij,
+ * and V_ijkl = 0 unless 2m_i+2m_j = 2m_k+2m_l and {tau_i,tau_j} = {tau_k,tau_l}
+ * -> DMRG_ERR_HAMILTONIAN naming the first offending (i,j,k,l).
+ * Target (n_p, n_n, 2M): DMRG_ERR_TARGET if no determinant has it.
+ * Reloading resets all DMRG state.  1 <= n_sites <= 64. */
+dmrg_status dmrg_load_hamiltonian(dmrg_ctx* ctx, int32_t n_sites, const int32_t* species,
+                                  const int32_t* two_m, const double* eps, const double* V,
+                                  int32_t n_p, int32_t n_n, int32_t two_M);
+
+/* One sweep: left-to-right over bonds 0..N-2 then right-to-left back to 0,
+ * keeping at most D block states.  `ordering` (host, a permutation of
+ * 0..N-1; NULL = natural order) maps chain position -> site.  The first call,
+ * or a call with a different ordering, (re)initialises the blocks; D may
+ * change between calls.  `out` (nullable) receives the sweep statistics.
+ * Returns DMRG_WARN_NOT_CONVERGED if a Davidson solve hit its limit. */
+dmrg_status dmrg_sweep(dmrg_ctx* ctx, const int32_t* ordering, int32_t D, dmrg_sweep_stats* out);
+
+/* Advance at most n_steps two-site steps of the sweep schedule (a full sweep
+ * is 2(N-1) steps), continuing from where the previous call stopped. */
+dmrg_status dmrg_sweep_steps(dmrg_ctx* ctx, const int32_t* ordering, int32_t D, int32_t n_steps,
+                             dmrg_sweep_stats* out);
+
+/* Layout of psi at the current bond (sites bond, bond+1 explicit).  psi is a
+ * list of dense row-major blocks, one per S sector q (S = chain sites
+ * 0..bond), in ascending (n_p, n_n, 2M) order; block q has
+ * sector_dims[2s] rows (S states: site `bond` empty part first) and
+ * sector_dims[2s+1] columns (E states of sector target - q: site `bond+1`
+ * empty part first).  Call with NULL arrays to get n_sectors first. */
+dmrg_status dmrg_heff_layout(dmrg_ctx* ctx, int32_t* bond, int64_t* dim, int32_t* n_sectors,
+                             int32_t* sector_qn, int64_t* sector_dims);
+
+/* y = H_eff psi at the current bond (the superblock Hamiltonian P^T H P in
+ * the current block bases).  psi_in, psi_out: device pointers, FP64, `dim`
+ * elements in the dmrg_heff_layout order, caller-owned, must not overlap.
+ * The sector GEMMs run in `precision` (dmrg_precision); I/O stays FP64.
+ * Asynchronous on the context stream; synchronise the stream before reading.
+ * DMRG_ERR_STATE before the first sweep step. */
+dmrg_status dmrg_heff_apply(dmrg_ctx* ctx, const double* psi_in, double* psi_out, int32_t precision);
+
+/* FP64 sweep energy (MeV) of the last completed sweep.  DMRG_ERR_STATE before. */
+dmrg_status dmrg_energy(dmrg_ctx* ctx, double* E);
+
+/* Current superblock state (host copy, dmrg_heff_layout order). */
+dmrg_status dmrg_get_psi(dmrg_ctx* ctx, double* psi_host);
+
+/* Test support: with select_basis = 1 every block state is one determinant;
+ * configs[x] (host, dim entries) receives the determinant of psi component x
+ * as a bit mask over chain positions (bit a = site ordering[a]); the state is
+ * prod_{a in mask, ascending} c+_{ordering[a]} |0>.  DMRG_ERR_STATE otherwise. */
+dmrg_status dmrg_heff_configs(dmrg_ctx* ctx, uint64_t* configs);
+
+/* Advance n contexts (same device) by one sweep each with their own ordering
+ * (orderings[i] may be NULL) and D[i].  Per-context status in out[i].status;
+ * returns the first error, else the largest warning. */
+dmrg_status dmrg_sweep_many(dmrg_ctx** ctxs, int32_t n, const int32_t* const* orderings,
+                            const int32_t* D, dmrg_sweep_stats* out);
+
+const char* dmrg_status_string(dmrg_status s);
+const char* dmrg_last_error(const dmrg_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,127 @@
+// device.h - the device primitives the host engine issues, implemented in
+// device.hip for gfx950.  Every call is asynchronous on the context stream
+// unless it says otherwise; integer returns are 0 on success.
+//
+// Work is described by flat task lists (uploaded once per bond and reused by
+// every Davidson product) that reference up to kMaxBufs base pointers; an
+// offset is counted in elements of the buffer's element type.
+#pragma once
+#include <cstddef>
+#include <cstdint>
+
+namespace dmrgdev {
+
+constexpr int kMaxBufs = 8;
+
+struct Ctx;
+
+int ctx_create(int device, void* stream, Ctx** out, char* err, size_t errlen);
+void ctx_destroy(Ctx* c);
+const char* last_error(Ctx* c);
+
+void* alloc(Ctx* c, size_t bytes);          // nullptr on failure
+void release(Ctx* c, void* p);
+int h2d(Ctx* c, void* dst, const void* src, size_t bytes);   // returns when src may be reused
+int d2h(Ctx* c, void* dst, const void* src, size_t bytes);   // synchronous
+int d2d(Ctx* c, void* dst, const void* src, size_t bytes);
+int fill(Ctx* c, double* x, int64_t n, double v);
+int sync(Ctx* c);
+
+// timing on the context stream
+int event_record(Ctx* c, int slot);                   // slot < 64
+double event_elapsed(Ctx* c, int slot0, int slot1);   // seconds, synchronises
+
+// ---------------------------------------------------------------- GEMM
+// One output tile per task:
+//   C[m0:m0+mt, n0:n0+nt] = beta*C + sum_chunks alpha * op(A)[m0.., :K] op(B)[:K, n0..]
+// op(A) is M x K: stored row-major M x K (a_trans = 0) or K x M (a_trans = 1).
+// op(B) is K x N: stored row-major K x N (b_trans = 0) or N x K (b_trans = 1).
+// Offsets point at the block origins (row 0, column 0 of op(.)).
+struct GemmChunk {
+    double alpha;
+    int64_t a_off, b_off;
+    int32_t lda, ldb, K;
+    uint8_t a_buf, b_buf, a_trans, b_trans;
+};
+struct GemmTask {
+    int64_t c_off;
+    int32_t ldc, m0, n0, mt, nt;
+    int32_t chunk_begin, chunk_end;
+    uint8_t c_buf, beta, pad0, pad1;
+};
+constexpr int kTileM = 64;
+constexpr int kTileN = 64;
+
+enum Prec { P_F64 = 0, P_F32 = 1, P_BF16 = 2 };
+
+// A and B of one launch share a precision (ab_prec); C is c_prec.  Supported:
+// (F64, F64), (F32, F32), (BF16, F32), (BF16, BF16).  Accumulation is FP64
+// for F64 operands and FP32 otherwise.
+int gemm(Ctx* c, int ab_prec, int c_prec, void* const* bufs, const GemmTask* d_tasks, int ntasks,
+         const GemmChunk* d_chunks);
+
+// ------------------------------------------------------- linear combination
+// dst[r0+r, c0+c] = sum_terms coef * src(r0+r, c0+c) with src(r, c) =
+// S[r*ld + c], S[c*ld + r] (trans) or delta_rc (ident).  FP64.
+struct LcTerm {
+    double coef;
+    int64_t src_off;
+    int32_t ld;
+    uint8_t buf, trans, ident, pad;
+};
+struct LcTask {
+    int64_t dst_off;
+    int32_t ld, r0, c0, mt, nt;
+    int32_t t_begin, t_end;
+    uint8_t buf, pad0, pad1, pad2;
+};
+constexpr int kLcTile = 32;
+int lincomb(Ctx* c, double* const* bufs, const LcTask* d_tasks, int ntasks, const LcTerm* d_terms);
+
+// -------------------------------------------------------- H_eff diagonal
+// d[r0+r, c0+c] = sum_terms coef * a(r0+r) * b(c0+c), a(x) = A[a_off + x*a_step]
+// (or 1 if a_ident), likewise b.  FP64.
+struct DiagTerm {
+    double coef;
+    int64_t a_off, b_off;
+    int32_t a_step, b_step;
+    uint8_t a_buf, b_buf, a_ident, b_ident;
+};
+struct DiagTask {
+    int64_t d_off;
+    int32_t ld, r0, c0, mt, nt;
+    int32_t t_begin, t_end;
+};
+int diag(Ctx* c, double* const* bufs, const DiagTask* d_tasks, int ntasks, const DiagTerm* d_terms);
+
+// ----------------------------------------------------- FP64 vector kernels
+// V holds nvec vectors of length n at stride ldv.
+// d_out[v * ostride] = V_v . w
+int dots(Ctx* c, const double* V, int64_t ldv, int nvec, const double* w, int64_t n, double* d_out,
+         int ostride = 1);
+// out = (accumulate ? out : 0) + scale * sum_v coef[v] V_v      (coef on device)
+int combine(Ctx* c, const double* V, int64_t ldv, int nvec, const double* d_coef, double scale,
+            int64_t n, double* out, int accumulate);
+// r = hx - theta * x ; also writes |r|^2 to d_norm2
+int residual(Ctx* c, const double* hx, const double* x, const double* d_theta, int64_t n,
+             double* r, double* d_norm2);
+// t = r / (d - theta), |d - theta| clamped to >= 1e-12 keeping its sign
+int precond(Ctx* c, const double* r, const double* d, const double* d_theta, int64_t n, double* t);
+// x *= 1/sqrt(*d_norm2)
+int scale_inv_norm(Ctx* c, double* x, int64_t n, const double* d_norm2);
+// y = x * (1/sqrt(*d_norm2))
+int copy_scaled_inv_norm(Ctx* c, const double* x, int64_t n, const double* d_norm2, double* y);
+// lowest eigenpair of the symmetrised k x k matrix (G + G^T)/2, row stride ldg
+int small_eigh(Ctx* c, const double* d_G, int k, int ldg, double* d_theta, double* d_s);
+// type conversion of n elements
+int convert(Ctx* c, int from_prec, const void* src, int to_prec, void* dst, int64_t n);
+
+// ------------------------------------------------- dense symmetric eigen
+// A (n x n, symmetric) is overwritten with eigenvectors: row e of the
+// row-major array is the eigenvector of w[e]; w ascending.
+int syevd(Ctx* c, int n, double* A, double* w);
+// U[r, col] = s_col * E[idx[col], r] (E rows = eigenvectors of length n),
+// s_col = +-1 making the first largest-magnitude entry positive.
+int gather_evecs(Ctx* c, const double* E, int n, const int32_t* d_idx, int k, double* U);
+
+}  // namespace dmrgdev

@@ -1,0 +1,893 @@
+// device.hip - gfx950 kernels and launchers behind device.h.
+//
+// Hot path: `gemm` is a grouped, multi-chunk GEMM.  One work-group (4 waves)
+// owns one 64x64 output tile of one sector block and accumulates every chunk
+// (term x input sub-block) that lands on it, so an output is written once,
+// without atomics.  Operands are staged through LDS in 16-deep K slices
+// (transposes are resolved while staging) and multiplied on the matrix cores:
+// v_mfma_f64_16x16x4f64 (FP64), v_mfma_f32_16x16x4f32 (FP32) and
+// v_mfma_f32_16x16x32_bf16 (BF16 operands, FP32 accumulation).  Each wave
+// holds a 32x32 quarter of the tile as 2x2 MFMA blocks.
+#include <hip/hip_runtime.h>
+#include <rocblas/rocblas.h>
+#include <rocsolver/rocsolver.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "device.h"
+
+namespace dmrgdev {
+
+struct Ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    rocblas_handle blas = nullptr;
+    hipEvent_t ev[64] = {};
+    std::string err;
+    // scratch for reductions and the eigensolver
+    double* red = nullptr;
+    size_t red_cap = 0;
+    double* syev_e = nullptr;
+    size_t syev_cap = 0;
+    int* info = nullptr;
+};
+
+static int seterr(Ctx* c, const char* what, hipError_t e) {
+    c->err = std::string(what) + ": " + hipGetErrorString(e);
+    return 1;
+}
+#define HIPCHK(c, x)                                  \
+    do {                                              \
+        hipError_t _e = (x);                          \
+        if (_e != hipSuccess) return seterr(c, #x, _e); \
+    } while (0)
+#define LAUNCHCHK(c)                                                   \
+    do {                                                               \
+        hipError_t _e = hipGetLastError();                             \
+        if (_e != hipSuccess) return seterr(c, "kernel launch", _e);   \
+    } while (0)
+
+int ctx_create(int device, void* stream, Ctx** out, char* err, size_t errlen) {
+    auto fail = [&](const char* m) {
+        if (err && errlen) snprintf(err, errlen, "%s", m);
+        return 1;
+    };
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || n == 0) return fail("no HIP device visible");
+    if (device < 0 || device >= n) return fail("device ordinal out of range");
+    if (hipSetDevice(device) != hipSuccess) return fail("hipSetDevice failed");
+    Ctx* c = new Ctx();
+    c->device = device;
+    if (stream) {
+        c->stream = (hipStream_t)stream;
+    } else {
+        if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+            delete c;
+            return fail("hipStreamCreate failed");
+        }
+        c->own_stream = true;
+    }
+    for (auto& e : c->ev)
+        if (hipEventCreate(&e) != hipSuccess) {
+            delete c;
+            return fail("hipEventCreate failed");
+        }
+    if (rocblas_create_handle(&c->blas) != rocblas_status_success) {
+        delete c;
+        return fail("rocblas_create_handle failed");
+    }
+    rocblas_set_stream(c->blas, c->stream);
+    if (hipMalloc(&c->info, sizeof(int)) != hipSuccess) {
+        delete c;
+        return fail("hipMalloc failed");
+    }
+    *out = c;
+    return 0;
+}
+
+void ctx_destroy(Ctx* c) {
+    if (!c) return;
+    hipSetDevice(c->device);
+    hipStreamSynchronize(c->stream);
+    if (c->blas) rocblas_destroy_handle(c->blas);
+    for (auto& e : c->ev)
+        if (e) hipEventDestroy(e);
+    if (c->red) hipFree(c->red);
+    if (c->syev_e) hipFree(c->syev_e);
+    if (c->info) hipFree(c->info);
+    if (c->own_stream) hipStreamDestroy(c->stream);
+    delete c;
+}
+
+const char* last_error(Ctx* c) { return c->err.c_str(); }
+
+void* alloc(Ctx* c, size_t bytes) {
+    void* p = nullptr;
+    if (hipMalloc(&p, bytes ? bytes : 8) != hipSuccess) {
+        hipGetLastError();
+        c->err = "hipMalloc failed";
+        return nullptr;
+    }
+    return p;
+}
+void release(Ctx*, void* p) {
+    if (p) hipFree(p);
+}
+int h2d(Ctx* c, void* dst, const void* src, size_t bytes) {
+    HIPCHK(c, hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return 0;
+}
+int d2h(Ctx* c, void* dst, const void* src, size_t bytes) {
+    HIPCHK(c, hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return 0;
+}
+int d2d(Ctx* c, void* dst, const void* src, size_t bytes) {
+    if (!bytes) return 0;
+    HIPCHK(c, hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, c->stream));
+    return 0;
+}
+int sync(Ctx* c) {
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return 0;
+}
+int event_record(Ctx* c, int slot) {
+    HIPCHK(c, hipEventRecord(c->ev[slot], c->stream));
+    return 0;
+}
+double event_elapsed(Ctx* c, int a, int b) {
+    float ms = 0.f;
+    if (hipEventSynchronize(c->ev[b]) != hipSuccess) return 0.0;
+    if (hipEventElapsedTime(&ms, c->ev[a], c->ev[b]) != hipSuccess) return 0.0;
+    return ms * 1e-3;
+}
+
+// -------------------------------------------------------------- helpers
+__global__ void k_fill(double* __restrict__ x, int64_t n, double v) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t s = (int64_t)gridDim.x * blockDim.x;
+    for (; i < n; i += s) x[i] = v;
+}
+static unsigned grid_for(int64_t n, int per = 256, unsigned cap = 8192) {
+    int64_t g = (n + per - 1) / per;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (unsigned)g;
+}
+int fill(Ctx* c, double* x, int64_t n, double v) {
+    if (n <= 0) return 0;
+    hipLaunchKernelGGL(k_fill, dim3(grid_for(n)), dim3(256), 0, c->stream, x, n, v);
+    LAUNCHCHK(c);
+    return 0;
+}
+
+// bf16 as raw 16-bit storage; round to nearest even on conversion
+typedef unsigned short bf16_t;
+__device__ __forceinline__ bf16_t f2bf(float f) {
+    unsigned u = __float_as_uint(f);
+    if ((u & 0x7f800000u) == 0x7f800000u) return (bf16_t)(u >> 16);   // inf / nan
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (bf16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(bf16_t h) { return __uint_as_float(((unsigned)h) << 16); }
+
+// ================================================================ GEMM
+struct Bufs {
+    void* p[kMaxBufs];
+};
+
+typedef double d4_t __attribute__((ext_vector_type(4)));
+typedef float f4_t __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8_t __attribute__((ext_vector_type(8)));
+
+constexpr int TM = kTileM, TN = kTileN;   // 64 x 64 output tile
+constexpr int NTH = 256;                  // 4 waves
+
+// ---- FP64 / FP32: K slice 16, LDS As[k][m], Bs[k][n] (k-major, padded)
+template <class T> struct MmaTraits;
+// A operand: lane l holds A[l%16][l/16]; B operand: lane l holds B[l/16][l%16].
+// Result register r of lane l is D[row(l, r)][l%16]; the row map differs
+// between the FP64 and FP32 instructions (measured on gfx950).
+template <> struct MmaTraits<double> {
+    typedef d4_t acc_t;
+    static __device__ __forceinline__ acc_t mma(double a, double b, acc_t c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int lane, int r) { return (lane >> 4) + 4 * r; }
+};
+template <> struct MmaTraits<float> {
+    typedef f4_t acc_t;
+    static __device__ __forceinline__ acc_t mma(float a, float b, acc_t c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane >> 4) + r; }
+};
+
+template <class T>
+__device__ __forceinline__ void stage_a(T* __restrict__ As, const T* __restrict__ A, const GemmChunk& ch,
+                                        int m0, int mt, int k0, T alpha, int tid) {
+    constexpr int BK = 16, LDA_S = TM + 1;
+    if (!ch.a_trans) {
+        // A row-major M x K: thread -> row tid/4, k 4*(tid%4)..+3
+        int m = tid >> 2, kk = (tid & 3) * 4;
+        const T* src = A + (int64_t)(m0 + m) * ch.lda + k0 + kk;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            int k = k0 + kk + u;
+            T v = (m < mt && k < ch.K) ? src[u] : T(0);
+            As[(kk + u) * LDA_S + m] = v * alpha;
+        }
+    } else {
+        // A stored K x M: thread -> k tid/16, m 4*(tid%16)..+3
+        int kk = tid >> 4, m = (tid & 15) * 4;
+        int k = k0 + kk;
+        const T* src = A + (int64_t)k * ch.lda + m0 + m;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            T v = (m + u < mt && k < ch.K) ? src[u] : T(0);
+            As[kk * LDA_S + m + u] = v * alpha;
+        }
+    }
+    (void)BK;
+}
+
+template <class T>
+__device__ __forceinline__ void stage_b(T* __restrict__ Bs, const T* __restrict__ B, const GemmChunk& ch,
+                                        int n0, int nt, int k0, int tid) {
+    constexpr int LDB_S = TN + 1;
+    if (!ch.b_trans) {
+        // B row-major K x N: thread -> k tid/16, n 4*(tid%16)..+3
+        int kk = tid >> 4, n = (tid & 15) * 4;
+        int k = k0 + kk;
+        const T* src = B + (int64_t)k * ch.ldb + n0 + n;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            T v = (n + u < nt && k < ch.K) ? src[u] : T(0);
+            Bs[kk * LDB_S + n + u] = v;
+        }
+    } else {
+        // B stored N x K: thread -> n tid/4, k 4*(tid%4)..+3
+        int n = tid >> 2, kk = (tid & 3) * 4;
+        const T* src = B + (int64_t)(n0 + n) * ch.ldb + k0 + kk;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            int k = k0 + kk + u;
+            T v = (n < nt && k < ch.K) ? src[u] : T(0);
+            Bs[(kk + u) * LDB_S + n] = v;
+        }
+    }
+}
+
+template <class T, class TC>
+__global__ void __launch_bounds__(NTH) k_gemm(Bufs bufs, const GemmTask* __restrict__ tasks,
+                                              const GemmChunk* __restrict__ chunks) {
+    typedef typename MmaTraits<T>::acc_t acc_t;
+    constexpr int BK = 16, LDA_S = TM + 1, LDB_S = TN + 1;
+    __shared__ T As[BK * LDA_S];
+    __shared__ T Bs[BK * LDB_S];
+    const GemmTask tk = tasks[blockIdx.x];
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6, lane = tid & 63;
+    const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;   // wave quadrant
+    acc_t acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = acc_t{0, 0, 0, 0};
+    for (int c = tk.chunk_begin; c < tk.chunk_end; ++c) {
+        const GemmChunk ch = chunks[c];
+        const T* A = (const T*)bufs.p[ch.a_buf] + ch.a_off;
+        const T* B = (const T*)bufs.p[ch.b_buf] + ch.b_off;
+        const T alpha = (T)ch.alpha;
+        for (int k0 = 0; k0 < ch.K; k0 += BK) {
+            stage_a<T>(As, A, ch, tk.m0, tk.mt, k0, alpha, tid);
+            stage_b<T>(Bs, B, ch, tk.n0, tk.nt, k0, tid);
+            __syncthreads();
+#pragma unroll
+            for (int ks = 0; ks < BK; ks += 4) {
+                const int kr = ks + (lane >> 4);
+                T av[2], bv[2];
+#pragma unroll
+                for (int a = 0; a < 2; ++a) av[a] = As[kr * LDA_S + wm + a * 16 + (lane & 15)];
+#pragma unroll
+                for (int b = 0; b < 2; ++b) bv[b] = Bs[kr * LDB_S + wn + b * 16 + (lane & 15)];
+#pragma unroll
+                for (int a = 0; a < 2; ++a)
+#pragma unroll
+                    for (int b = 0; b < 2; ++b) acc[a][b] = MmaTraits<T>::mma(av[a], bv[b], acc[a][b]);
+            }
+            __syncthreads();
+        }
+    }
+    // epilogue
+    TC* C = (TC*)bufs.p[tk.c_buf] + tk.c_off;
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                int row = wm + a * 16 + MmaTraits<T>::row(lane, r);
+                int col = wn + b * 16 + (lane & 15);
+                if (row < tk.mt && col < tk.nt) {
+                    TC* dst = C + (int64_t)(tk.m0 + row) * tk.ldc + tk.n0 + col;
+                    double v = (double)acc[a][b][r];
+                    if (tk.beta) v += (double)*dst;
+                    *dst = (TC)v;
+                }
+            }
+}
+
+// ---- BF16: K slice 32, one v_mfma_f32_16x16x32_bf16 per 16x16 block and slice
+// LDS holds fp32-converted-to-bf16 values as As[m][k] and Bs[n][k] (k fastest)
+// so that a lane's 8 consecutive k values are one 16-byte read.
+__device__ __forceinline__ void stage_a_bf(bf16_t* __restrict__ As, const bf16_t* __restrict__ A,
+                                           const GemmChunk& ch, int m0, int mt, int k0, float alpha, int tid) {
+    constexpr int BK = 32, LDS = BK + 8;
+    // 64 rows x 32 k = 2048 elements, 8 per thread
+    if (!ch.a_trans) {
+        int m = tid >> 2, kk = (tid & 3) * 8;
+        const bf16_t* src = A + (int64_t)(m0 + m) * ch.lda + k0 + kk;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            int k = k0 + kk + u;
+            float v = (m < mt && k < ch.K) ? bf2f(src[u]) : 0.f;
+            As[m * LDS + kk + u] = f2bf(v * alpha);
+        }
+    } else {
+        int kk = tid >> 3, m = (tid & 7) * 8;
+        int k = k0 + kk;
+        const bf16_t* src = A + (int64_t)k * ch.lda + m0 + m;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            float v = (m + u < mt && k < ch.K) ? bf2f(src[u]) : 0.f;
+            As[(m + u) * LDS + kk] = f2bf(v * alpha);
+        }
+    }
+}
+__device__ __forceinline__ void stage_b_bf(bf16_t* __restrict__ Bs, const bf16_t* __restrict__ B,
+                                           const GemmChunk& ch, int n0, int nt, int k0, int tid) {
+    constexpr int BK = 32, LDS = BK + 8;
+    if (!ch.b_trans) {
+        int kk = tid >> 3, n = (tid & 7) * 8;
+        int k = k0 + kk;
+        const bf16_t* src = B + (int64_t)k * ch.ldb + n0 + n;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            bf16_t v = (n + u < nt && k < ch.K) ? src[u] : (bf16_t)0;
+            Bs[(n + u) * LDS + kk] = v;
+        }
+    } else {
+        int n = tid >> 2, kk = (tid & 3) * 8;
+        const bf16_t* src = B + (int64_t)(n0 + n) * ch.ldb + k0 + kk;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            int k = k0 + kk + u;
+            bf16_t v = (n < nt && k < ch.K) ? src[u] : (bf16_t)0;
+            Bs[n * LDS + kk + u] = v;
+        }
+    }
+}
+
+template <class TC>
+__global__ void __launch_bounds__(NTH) k_gemm_bf16(Bufs bufs, const GemmTask* __restrict__ tasks,
+                                                   const GemmChunk* __restrict__ chunks) {
+    constexpr int BK = 32, LDS = BK + 8;
+    __shared__ __attribute__((aligned(16))) bf16_t As[TM * LDS];
+    __shared__ __attribute__((aligned(16))) bf16_t Bs[TN * LDS];
+    const GemmTask tk = tasks[blockIdx.x];
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6, lane = tid & 63;
+    const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+    f4_t acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = f4_t{0, 0, 0, 0};
+    for (int c = tk.chunk_begin; c < tk.chunk_end; ++c) {
+        const GemmChunk ch = chunks[c];
+        const bf16_t* A = (const bf16_t*)bufs.p[ch.a_buf] + ch.a_off;
+        const bf16_t* B = (const bf16_t*)bufs.p[ch.b_buf] + ch.b_off;
+        const float alpha = (float)ch.alpha;
+        for (int k0 = 0; k0 < ch.K; k0 += BK) {
+            stage_a_bf(As, A, ch, tk.m0, tk.mt, k0, alpha, tid);
+            stage_b_bf(Bs, B, ch, tk.n0, tk.nt, k0, tid);
+            __syncthreads();
+            // lane: row/col lane%16, k 8*(lane/16)..+7
+            const int kq = 8 * (lane >> 4);
+            bf8_t av[2], bv[2];
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+                av[a] = *(const bf8_t*)&As[(wm + a * 16 + (lane & 15)) * LDS + kq];
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+                bv[b] = *(const bf8_t*)&Bs[(wn + b * 16 + (lane & 15)) * LDS + kq];
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < 2; ++b)
+                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[a], bv[b], acc[a][b], 0, 0, 0);
+            __syncthreads();
+        }
+    }
+    TC* C = (TC*)bufs.p[tk.c_buf] + tk.c_off;
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                int row = wm + a * 16 + 4 * (lane >> 4) + r;
+                int col = wn + b * 16 + (lane & 15);
+                if (row < tk.mt && col < tk.nt) {
+                    TC* dst = C + (int64_t)(tk.m0 + row) * tk.ldc + tk.n0 + col;
+                    float v = acc[a][b][r];
+                    if constexpr (sizeof(TC) == 4) {
+                        if (tk.beta) v += *(float*)dst;
+                        *(float*)dst = v;
+                    } else {
+                        if (tk.beta) v += bf2f(*(bf16_t*)dst);
+                        *(bf16_t*)dst = f2bf(v);
+                    }
+                }
+            }
+}
+
+int gemm(Ctx* c, int ab, int cp, void* const* bufs, const GemmTask* tasks, int ntasks, const GemmChunk* chunks) {
+    if (ntasks <= 0) return 0;
+    Bufs b;
+    for (int i = 0; i < kMaxBufs; ++i) b.p[i] = bufs[i];
+    dim3 grid(ntasks), block(NTH);
+    if (ab == P_F64 && cp == P_F64)
+        hipLaunchKernelGGL((k_gemm<double, double>), grid, block, 0, c->stream, b, tasks, chunks);
+    else if (ab == P_F32 && cp == P_F32)
+        hipLaunchKernelGGL((k_gemm<float, float>), grid, block, 0, c->stream, b, tasks, chunks);
+    else if (ab == P_BF16 && cp == P_F32)
+        hipLaunchKernelGGL((k_gemm_bf16<float>), grid, block, 0, c->stream, b, tasks, chunks);
+    else if (ab == P_BF16 && cp == P_BF16)
+        hipLaunchKernelGGL((k_gemm_bf16<bf16_t>), grid, block, 0, c->stream, b, tasks, chunks);
+    else {
+        c->err = "unsupported GEMM precision combination";
+        return 1;
+    }
+    LAUNCHCHK(c);
+    return 0;
+}
+
+// ====================================================== linear combination
+struct DBufs {
+    double* p[kMaxBufs];
+};
+
+__global__ void __launch_bounds__(256) k_lincomb(DBufs bufs, const LcTask* __restrict__ tasks,
+                                                 const LcTerm* __restrict__ terms) {
+    const LcTask tk = tasks[blockIdx.x];
+    const int tid = threadIdx.x;
+    const int r = tid >> 3, c4 = (tid & 7) * 4;   // 32 rows x 32 cols, 4 per thread
+    double acc[4] = {0, 0, 0, 0};
+    for (int t = tk.t_begin; t < tk.t_end; ++t) {
+        const LcTerm L = terms[t];
+        const int rr = tk.r0 + r;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int cc = tk.c0 + c4 + u;
+            if (r >= tk.mt || c4 + u >= tk.nt) continue;
+            double v;
+            if (L.ident) {
+                v = rr == cc ? 1.0 : 0.0;
+            } else {
+                const double* S = bufs.p[L.buf] + L.src_off;
+                v = L.trans ? S[(int64_t)cc * L.ld + rr] : S[(int64_t)rr * L.ld + cc];
+            }
+            acc[u] += L.coef * v;
+        }
+    }
+    double* D = bufs.p[tk.buf] + tk.dst_off;
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+        if (r < tk.mt && c4 + u < tk.nt) D[(int64_t)(tk.r0 + r) * tk.ld + tk.c0 + c4 + u] = acc[u];
+}
+
+int lincomb(Ctx* c, double* const* bufs, const LcTask* tasks, int ntasks, const LcTerm* terms) {
+    if (ntasks <= 0) return 0;
+    DBufs b;
+    for (int i = 0; i < kMaxBufs; ++i) b.p[i] = i < 2 ? bufs[i] : nullptr;
+    hipLaunchKernelGGL(k_lincomb, dim3(ntasks), dim3(256), 0, c->stream, b, tasks, terms);
+    LAUNCHCHK(c);
+    return 0;
+}
+
+// ========================================================== H_eff diagonal
+__global__ void __launch_bounds__(256) k_diag(DBufs bufs, const DiagTask* __restrict__ tasks,
+                                              const DiagTerm* __restrict__ terms) {
+    const DiagTask tk = tasks[blockIdx.x];
+    const int tid = threadIdx.x;
+    const int r = tid >> 3, c4 = (tid & 7) * 4;
+    double acc[4] = {0, 0, 0, 0};
+    for (int t = tk.t_begin; t < tk.t_end; ++t) {
+        const DiagTerm d = terms[t];
+        if (r >= tk.mt) continue;
+        double a = d.a_ident ? 1.0 : bufs.p[d.a_buf][d.a_off + (int64_t)(tk.r0 + r) * d.a_step];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if (c4 + u >= tk.nt) continue;
+            double b = d.b_ident ? 1.0 : bufs.p[d.b_buf][d.b_off + (int64_t)(tk.c0 + c4 + u) * d.b_step];
+            acc[u] += d.coef * a * b;
+        }
+    }
+    double* D = bufs.p[2] + tk.d_off;
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+        if (r < tk.mt && c4 + u < tk.nt) D[(int64_t)(tk.r0 + r) * tk.ld + tk.c0 + c4 + u] = acc[u];
+}
+
+int diag(Ctx* c, double* const* bufs, const DiagTask* tasks, int ntasks, const DiagTerm* terms) {
+    if (ntasks <= 0) return 0;
+    DBufs b;
+    for (int i = 0; i < kMaxBufs; ++i) b.p[i] = i < 3 ? bufs[i] : nullptr;
+    hipLaunchKernelGGL(k_diag, dim3(ntasks), dim3(256), 0, c->stream, b, tasks, terms);
+    LAUNCHCHK(c);
+    return 0;
+}
+
+// ============================================================ FP64 vectors
+constexpr int kDotBlocks = 512;
+
+// partial[v * gridDim.x + block] = sum over this block's slice of V_v . w
+__global__ void __launch_bounds__(256) k_dots_partial(const double* __restrict__ V, int64_t ldv, int nvec,
+                                                      const double* __restrict__ w, int64_t n,
+                                                      double* __restrict__ partial) {
+    __shared__ double sh[32][8];
+    double acc[32];
+#pragma unroll
+    for (int v = 0; v < 32; ++v) acc[v] = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const double wi = w[i];
+#pragma unroll
+        for (int v = 0; v < 32; ++v)
+            if (v < nvec) acc[v] += V[(int64_t)v * ldv + i] * wi;
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int v = 0; v < 32; ++v) {
+        if (v >= nvec) break;
+        double s = acc[v];
+        for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+        if (lane == 0) sh[v][wave] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x < nvec) {
+        double s = 0.0;
+        for (int x = 0; x < 4; ++x) s += sh[threadIdx.x][x];
+        partial[(int64_t)threadIdx.x * gridDim.x + blockIdx.x] = s;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_dots_final(const double* __restrict__ partial, int nblk,
+                                                    double* __restrict__ out, int ostride) {
+    __shared__ double sh[256];
+    const int v = blockIdx.x;
+    double s = 0.0;
+    for (int i = threadIdx.x; i < nblk; i += blockDim.x) s += partial[(int64_t)v * nblk + i];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[(int64_t)v * ostride] = sh[0];
+}
+
+static int ensure_red(Ctx* c, size_t elems) {
+    if (c->red_cap >= elems) return 0;
+    if (c->red) hipFree(c->red);
+    c->red = nullptr;
+    c->red_cap = 0;
+    HIPCHK(c, hipMalloc(&c->red, elems * sizeof(double)));
+    c->red_cap = elems;
+    return 0;
+}
+
+int dots(Ctx* c, const double* V, int64_t ldv, int nvec, const double* w, int64_t n, double* out, int ostride) {
+    if (nvec <= 0) return 0;
+    if (nvec > 32) {
+        c->err = "dots: at most 32 vectors";
+        return 1;
+    }
+    int nblk = (int)std::min<int64_t>(kDotBlocks, std::max<int64_t>(1, (n + 255) / 256));
+    if (ensure_red(c, (size_t)32 * kDotBlocks)) return 1;
+    hipLaunchKernelGGL(k_dots_partial, dim3(nblk), dim3(256), 0, c->stream, V, ldv, nvec, w, n, c->red);
+    LAUNCHCHK(c);
+    hipLaunchKernelGGL(k_dots_final, dim3(nvec), dim3(256), 0, c->stream, c->red, nblk, out, ostride);
+    LAUNCHCHK(c);
+    return 0;
+}
+
+__global__ void k_combine(const double* __restrict__ V, int64_t ldv, int nvec, const double* __restrict__ coef,
+                          double scale, int64_t n, double* __restrict__ out, int accumulate) {
+    __shared__ double cf[32];
+    if (threadIdx.x < nvec) cf[threadIdx.x] = coef[threadIdx.x] * scale;
+    __syncthreads();
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        double s = accumulate ? out[i] : 0.0;
+        for (int v = 0; v < nvec; ++v) s += cf[v] * V[(int64_t)v * ldv + i];
+        out[i] = s;
+    }
+}
+int combine(Ctx* c, const double* V, int64_t ldv, int nvec, const double* coef, double scale, int64_t n,
+            double* out, int accumulate) {
+    if (n <= 0 || nvec <= 0) return 0;
+    hipLaunchKernelGGL(k_combine, dim3(grid_for(n)), dim3(256), 0, c->stream, V, ldv, nvec, coef, scale, n, out,
+                       accumulate);
+    LAUNCHCHK(c);
+    return 0;
+}
+
+__global__ void k_residual(const double* __restrict__ hx, const double* __restrict__ x,
+                           const double* __restrict__ th, int64_t n, double* __restrict__ r) {
+    const double t = *th;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        r[i] = hx[i] - t * x[i];
+}
+int residual(Ctx* c, const double* hx, const double* x, const double* th, int64_t n, double* r, double* n2) {
+    hipLaunchKernelGGL(k_residual, dim3(grid_for(n)), dim3(256), 0, c->stream, hx, x, th, n, r);
+    LAUNCHCHK(c);
+    return dots(c, r, 0, 1, r, n, n2, 1);
+}
+
+__global__ void k_precond(const double* __restrict__ r, const double* __restrict__ d,
+                          const double* __restrict__ th, int64_t n, double* __restrict__ t) {
+    const double tt = *th;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        double den = d[i] - tt;
+        if (fabs(den) < 1e-12) den = den < 0.0 ? -1e-12 : 1e-12;
+        t[i] = r[i] / den;
+    }
+}
+int precond(Ctx* c, const double* r, const double* d, const double* th, int64_t n, double* t) {
+    hipLaunchKernelGGL(k_precond, dim3(grid_for(n)), dim3(256), 0, c->stream, r, d, th, n, t);
+    LAUNCHCHK(c);
+    return 0;
+}
+
+__global__ void k_scale_copy(const double* __restrict__ x, int64_t n, const double* __restrict__ n2,
+                             double* __restrict__ y) {
+    const double f = 1.0 / sqrt(*n2);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        y[i] = x[i] * f;
+}
+int scale_inv_norm(Ctx* c, double* x, int64_t n, const double* n2) {
+    hipLaunchKernelGGL(k_scale_copy, dim3(grid_for(n)), dim3(256), 0, c->stream, x, n, n2, x);
+    LAUNCHCHK(c);
+    return 0;
+}
+int copy_scaled_inv_norm(Ctx* c, const double* x, int64_t n, const double* n2, double* y) {
+    hipLaunchKernelGGL(k_scale_copy, dim3(grid_for(n)), dim3(256), 0, c->stream, x, n, n2, y);
+    LAUNCHCHK(c);
+    return 0;
+}
+
+// Lowest eigenpair of a k x k symmetric matrix (k <= 32): one wave, cyclic
+// Jacobi with the round-robin pair schedule (k/2 disjoint rotations per round).
+__global__ void __launch_bounds__(64) k_small_eigh(const double* __restrict__ G, int k, int ldg,
+                                                   double* __restrict__ theta, double* __restrict__ s) {
+    __shared__ double A[32][33];
+    __shared__ double Vm[32][33];
+    __shared__ double cs[16][2];
+    __shared__ int pr[16][2];
+    __shared__ int order[32];
+    __shared__ double red[64];
+    const int t = threadIdx.x;
+    const int kk = (k + 1) & ~1;   // even size; a padded index is never rotated
+    for (int e = t; e < 32 * 32; e += 64) {
+        int i = e >> 5, j = e & 31;
+        double v = 0.0;
+        if (i < k && j < k) v = 0.5 * (G[i * ldg + j] + G[j * ldg + i]);
+        A[i][j] = v;
+        Vm[i][j] = i == j ? 1.0 : 0.0;
+    }
+    if (t < 32) order[t] = t;
+    __syncthreads();
+    for (int sweep = 0; sweep < 40; ++sweep) {
+        // convergence: off-diagonal norm vs total norm
+        double off = 0.0, tot = 0.0;
+        for (int e = t; e < k * k; e += 64) {
+            int i = e / k, j = e % k;
+            double v = A[i][j] * A[i][j];
+            tot += v;
+            if (i != j) off += v;
+        }
+        red[t] = off;
+        __syncthreads();
+        for (int o = 32; o > 0; o >>= 1) {
+            if (t < o) red[t] += red[t + o];
+            __syncthreads();
+        }
+        double offs = red[0];
+        __syncthreads();
+        red[t] = tot;
+        __syncthreads();
+        for (int o = 32; o > 0; o >>= 1) {
+            if (t < o) red[t] += red[t + o];
+            __syncthreads();
+        }
+        double tots = red[0];
+        __syncthreads();
+        if (offs <= 1e-32 * tots || offs < 1e-300) break;
+        for (int round = 0; round < kk - 1; ++round) {
+            if (t < kk / 2) {
+                int p = order[t], q = order[kk - 1 - t];
+                if (p > q) {
+                    int x = p;
+                    p = q;
+                    q = x;
+                }
+                pr[t][0] = p;
+                pr[t][1] = q;
+                double c = 1.0, sn = 0.0;
+                if (q < k) {
+                    double apq = A[p][q];
+                    if (fabs(apq) > 1e-300) {
+                        double th = (A[q][q] - A[p][p]) / (2.0 * apq);
+                        double tt = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+                        c = 1.0 / sqrt(tt * tt + 1.0);
+                        sn = tt * c;
+                    }
+                }
+                cs[t][0] = c;
+                cs[t][1] = sn;
+            }
+            __syncthreads();
+            // columns: A[:, p], A[:, q] and V
+            for (int e = t; e < (kk / 2) * k; e += 64) {
+                int pi = e / k, i = e % k;
+                int p = pr[pi][0], q = pr[pi][1];
+                if (q >= k) continue;
+                double c = cs[pi][0], sn = cs[pi][1];
+                double aip = A[i][p], aiq = A[i][q];
+                A[i][p] = c * aip - sn * aiq;
+                A[i][q] = sn * aip + c * aiq;
+                double vip = Vm[i][p], viq = Vm[i][q];
+                Vm[i][p] = c * vip - sn * viq;
+                Vm[i][q] = sn * vip + c * viq;
+            }
+            __syncthreads();
+            // rows: A[p, :], A[q, :]
+            for (int e = t; e < (kk / 2) * k; e += 64) {
+                int pi = e / k, j = e % k;
+                int p = pr[pi][0], q = pr[pi][1];
+                if (q >= k) continue;
+                double c = cs[pi][0], sn = cs[pi][1];
+                double apj = A[p][j], aqj = A[q][j];
+                A[p][j] = c * apj - sn * aqj;
+                A[q][j] = sn * apj + c * aqj;
+            }
+            __syncthreads();
+            // rotate the round-robin order (index 0 fixed)
+            if (t == 0) {
+                int last = order[kk - 1];
+                for (int x = kk - 1; x > 1; --x) order[x] = order[x - 1];
+                order[1] = last;
+            }
+            __syncthreads();
+        }
+    }
+    if (t == 0) {
+        int b = 0;
+        for (int i = 1; i < k; ++i)
+            if (A[i][i] < A[b][b]) b = i;
+        red[0] = A[b][b];
+        pr[0][0] = b;
+    }
+    __syncthreads();
+    int b = pr[0][0];
+    if (t == 0) *theta = red[0];
+    if (t < k) s[t] = Vm[t][b];
+}
+int small_eigh(Ctx* c, const double* G, int k, int ldg, double* theta, double* s) {
+    if (k < 1 || k > 32) {
+        c->err = "small_eigh: k must be in 1..32";
+        return 1;
+    }
+    hipLaunchKernelGGL(k_small_eigh, dim3(1), dim3(64), 0, c->stream, G, k, ldg, theta, s);
+    LAUNCHCHK(c);
+    return 0;
+}
+
+// ============================================================ conversions
+__global__ void k_f64_to_f32(const double* __restrict__ x, float* __restrict__ y, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        y[i] = (float)x[i];
+}
+__global__ void k_f64_to_bf16(const double* __restrict__ x, bf16_t* __restrict__ y, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        y[i] = f2bf((float)x[i]);
+}
+__global__ void k_f32_to_f64(const float* __restrict__ x, double* __restrict__ y, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        y[i] = (double)x[i];
+}
+int convert(Ctx* c, int fp, const void* src, int tp, void* dst, int64_t n) {
+    if (n <= 0) return 0;
+    dim3 g(grid_for(n)), b(256);
+    if (fp == P_F64 && tp == P_F32)
+        hipLaunchKernelGGL(k_f64_to_f32, g, b, 0, c->stream, (const double*)src, (float*)dst, n);
+    else if (fp == P_F64 && tp == P_BF16)
+        hipLaunchKernelGGL(k_f64_to_bf16, g, b, 0, c->stream, (const double*)src, (bf16_t*)dst, n);
+    else if (fp == P_F32 && tp == P_F64)
+        hipLaunchKernelGGL(k_f32_to_f64, g, b, 0, c->stream, (const float*)src, (double*)dst, n);
+    else {
+        c->err = "unsupported conversion";
+        return 1;
+    }
+    LAUNCHCHK(c);
+    return 0;
+}
+
+// ================================================ dense symmetric eigen
+int syevd(Ctx* c, int n, double* A, double* w) {
+    if (n <= 0) return 0;
+    if (c->syev_cap < (size_t)n) {
+        if (c->syev_e) hipFree(c->syev_e);
+        c->syev_e = nullptr;
+        c->syev_cap = 0;
+        HIPCHK(c, hipMalloc(&c->syev_e, (size_t)n * sizeof(double)));
+        c->syev_cap = n;
+    }
+    rocblas_status st = rocsolver_dsyevd(c->blas, rocblas_evect_original, rocblas_fill_upper, n, A, n, w,
+                                         c->syev_e, c->info);
+    if (st != rocblas_status_success) {
+        c->err = std::string("rocsolver_dsyevd failed: ") + rocblas_status_to_string(st);
+        return 1;
+    }
+    return 0;
+}
+
+// one block per kept column: sign so that the first largest-|.| entry is positive
+__global__ void __launch_bounds__(256) k_gather_evecs(const double* __restrict__ E, int n,
+                                                      const int32_t* __restrict__ idx, int k,
+                                                      double* __restrict__ U) {
+    __shared__ double bv[256];
+    __shared__ int bi[256];
+    const int col = blockIdx.x;
+    const double* e = E + (int64_t)idx[col] * n;
+    double best = -1.0;
+    int besti = 0x7fffffff;
+    for (int r = threadIdx.x; r < n; r += blockDim.x) {
+        double a = fabs(e[r]);
+        if (a > best || (a == best && r < besti)) {
+            best = a;
+            besti = r;
+        }
+    }
+    bv[threadIdx.x] = best;
+    bi[threadIdx.x] = besti;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) {
+            double a = bv[threadIdx.x + o];
+            int ai = bi[threadIdx.x + o];
+            if (a > bv[threadIdx.x] || (a == bv[threadIdx.x] && ai < bi[threadIdx.x])) {
+                bv[threadIdx.x] = a;
+                bi[threadIdx.x] = ai;
+            }
+        }
+        __syncthreads();
+    }
+    const double sg = e[bi[0]] < 0.0 ? -1.0 : 1.0;
+    for (int r = threadIdx.x; r < n; r += blockDim.x) U[(int64_t)r * k + col] = sg * e[r];
+}
+int gather_evecs(Ctx* c, const double* E, int n, const int32_t* idx, int k, double* U) {
+    if (k <= 0) return 0;
+    hipLaunchKernelGGL(k_gather_evecs, dim3(k), dim3(256), 0, c->stream, E, n, idx, k, U);
+    LAUNCHCHK(c);
+    return 0;
+}
+
+}  // namespace dmrgdev

@@ -1,0 +1,2080 @@
+// engine.cpp - host control of the two-site DMRG hot path.
+//
+// Structure of one two-site step at bond b (sites b, b+1 explicit):
+//   S = L_b * s_b and E = s_{b+1} * R_{b+2} are "enlarged" blocks whose states
+//   are grouped by (base-block sector, site occupation).  Their operators are
+//   linear combinations of base-block operators times 2x2 site operators
+//   (blocking), written here as formula lists and executed on the device as
+//   scaled block copies.  H_eff psi is a sum of terms op(A) psi op(B)^T over
+//   S- and E-operators (complementary operators carry the two-body sums),
+//   executed as two grouped GEMM launches.  The lowest eigenpair is found by
+//   Davidson; the S (or E) reduced density matrix is diagonalised per sector,
+//   the D largest weights are kept, the operators renormalised (U^T O U), and
+//   the state is carried to the next bond as the next initial guess.
+#include "engine.h"
+
+#include <algorithm>
+#include <cstdio>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <set>
+#include <sstream>
+
+namespace dm {
+
+using dmrgdev::DiagTask;
+using dmrgdev::DiagTerm;
+using dmrgdev::GemmChunk;
+using dmrgdev::GemmTask;
+using dmrgdev::LcTask;
+using dmrgdev::LcTerm;
+
+// ---------------------------------------------------------------- hashing
+// SplitMix64 (Steele, Lea, Flood 2014) chained over the key fields.
+static inline uint64_t splitmix64(uint64_t x) {
+    uint64_t z = x + 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+static uint64_t hkey(std::initializer_list<int64_t> vals) {
+    uint64_t h = 0;
+    for (int64_t v : vals) h = splitmix64(h ^ (uint64_t)v);
+    return h;
+}
+static inline double u01(uint64_t h) { return (double)(h >> 11) * (1.0 / 9007199254740992.0); }
+
+static double now() {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// ----------------------------------------------------------------- memory
+Buf& Buf::operator=(Buf&& o) noexcept {
+    if (this != &o) {
+        reset();
+        eng = o.eng;
+        p = o.p;
+        bytes = o.bytes;
+        o.p = nullptr;
+        o.bytes = 0;
+    }
+    return *this;
+}
+void Buf::reset() {
+    if (p && eng) eng->dfree(p, bytes);
+    p = nullptr;
+    bytes = 0;
+}
+
+void* Engine::dalloc(size_t bytes) {
+    if (opt_.mem_cap_bytes && mem_used_ + bytes > opt_.mem_cap_bytes) return nullptr;
+    void* p = dmrgdev::alloc(dev_, bytes ? bytes : 8);
+    if (p) mem_used_ += bytes;
+    return p;
+}
+void Engine::dfree(void* p, size_t bytes) {
+    dmrgdev::release(dev_, p);
+    mem_used_ -= bytes;
+}
+dmrg_status Engine::alloc_buf(Buf& b, size_t bytes) {
+    b.reset();
+    b.p = dalloc(bytes);
+    if (!b.p) {
+        std::ostringstream s;
+        s << "device allocation of " << bytes << " bytes failed (in use " << mem_used_ << ")";
+        return fail(DMRG_ERR_OUT_OF_MEMORY, s.str());
+    }
+    b.eng = this;
+    b.bytes = bytes;
+    return DMRG_OK;
+}
+template <class T> dmrg_status Engine::upload(Buf& b, const std::vector<T>& v) {
+    dmrg_status st = alloc_buf(b, std::max<size_t>(v.size() * sizeof(T), 8));
+    if (st) return st;
+    if (!v.empty() && dmrgdev::h2d(dev_, b.p, v.data(), v.size() * sizeof(T)))
+        return fail(DMRG_ERR_DEVICE, dmrgdev::last_error(dev_));
+    return DMRG_OK;
+}
+
+Engine::~Engine() {
+    cur_.reset();
+    L_.clear();
+    R_.clear();
+}
+
+#define TRY(x)                        \
+    do {                              \
+        dmrg_status _s = (x);         \
+        if (_s < 0) return _s;        \
+    } while (0)
+#define DEV(x)                                                         \
+    do {                                                               \
+        if ((x) != 0) return fail(DMRG_ERR_DEVICE, dmrgdev::last_error(dev_)); \
+    } while (0)
+
+// ------------------------------------------------------ GEMM plan builder
+struct GB {
+    std::vector<GemmTask> tasks;
+    std::vector<GemmChunk> chunks;
+    int64_t cb = 0;
+    double flops = 0.0;
+    void begin() { cb = (int64_t)chunks.size(); }
+    void chunk(double alpha, int abuf, int64_t aoff, int lda, bool atr, int bbuf, int64_t boff, int ldb,
+               bool btr, int K) {
+        GemmChunk c;
+        c.alpha = alpha;
+        c.a_off = aoff;
+        c.b_off = boff;
+        c.lda = lda;
+        c.ldb = ldb;
+        c.K = K;
+        c.a_buf = (uint8_t)abuf;
+        c.b_buf = (uint8_t)bbuf;
+        c.a_trans = atr;
+        c.b_trans = btr;
+        chunks.push_back(c);
+    }
+    void end(int cbuf, int64_t coff, int ldc, int M, int Nn, int beta) {
+        int64_t ce = (int64_t)chunks.size();
+        for (int64_t x = cb; x < ce; ++x) flops += 2.0 * M * Nn * chunks[x].K;
+        for (int m0 = 0; m0 < M; m0 += dmrgdev::kTileM)
+            for (int n0 = 0; n0 < Nn; n0 += dmrgdev::kTileN) {
+                GemmTask t;
+                t.c_off = coff;
+                t.ldc = ldc;
+                t.m0 = m0;
+                t.n0 = n0;
+                t.mt = std::min(dmrgdev::kTileM, M - m0);
+                t.nt = std::min(dmrgdev::kTileN, Nn - n0);
+                t.chunk_begin = (int32_t)cb;
+                t.chunk_end = (int32_t)ce;
+                t.c_buf = (uint8_t)cbuf;
+                t.beta = (uint8_t)beta;
+                t.pad0 = t.pad1 = 0;
+                tasks.push_back(t);
+            }
+    }
+};
+
+dmrg_status Engine::run_gemm(int prec, void* const* bufs, const GemmPlan& p, int cprec) {
+    if (p.ntasks == 0) return DMRG_OK;
+    if (cprec < 0) cprec = prec == dmrgdev::P_BF16 ? dmrgdev::P_F32 : prec;
+    DEV(dmrgdev::gemm(dev_, prec, cprec, bufs, p.tasks.as<GemmTask>(), p.ntasks, p.chunks.as<GemmChunk>()));
+    return DMRG_OK;
+}
+
+static dmrg_status finish_plan(Engine& e, GB& g, GemmPlan& p) {
+    p.ntasks = (int)g.tasks.size();
+    p.nchunks = (int64_t)g.chunks.size();
+    p.flops = g.flops;
+    dmrg_status st = e.upload(p.tasks, g.tasks);
+    if (st) return st;
+    return e.upload(p.chunks, g.chunks);
+}
+
+// ------------------------------------------------ linear-combination builder
+struct LB {
+    std::vector<LcTask> tasks;
+    std::vector<LcTerm> terms;
+    void block(int dbuf, int64_t doff, int rows, int cols, const std::vector<LcTerm>& ts) {
+        int32_t t0 = (int32_t)terms.size();
+        terms.insert(terms.end(), ts.begin(), ts.end());
+        int32_t t1 = (int32_t)terms.size();
+        for (int r0 = 0; r0 < rows; r0 += dmrgdev::kLcTile)
+            for (int c0 = 0; c0 < cols; c0 += dmrgdev::kLcTile) {
+                LcTask t;
+                t.dst_off = doff;
+                t.ld = cols;
+                t.r0 = r0;
+                t.c0 = c0;
+                t.mt = std::min(dmrgdev::kLcTile, rows - r0);
+                t.nt = std::min(dmrgdev::kLcTile, cols - c0);
+                t.t_begin = t0;
+                t.t_end = t1;
+                t.buf = (uint8_t)dbuf;
+                t.pad0 = t.pad1 = t.pad2 = 0;
+                tasks.push_back(t);
+            }
+    }
+    dmrg_status run(Engine& e, double* const* bufs) {
+        if (tasks.empty()) return DMRG_OK;
+        Buf dt, dterm;
+        dmrg_status st = e.upload(dt, tasks);
+        if (st) return st;
+        st = e.upload(dterm, terms);
+        if (st) return st;
+        if (dmrgdev::lincomb(e.dev(), bufs, dt.as<LcTask>(), (int)tasks.size(), dterm.as<LcTerm>()))
+            return e.fail(DMRG_ERR_DEVICE, dmrgdev::last_error(e.dev()));
+        // the task lists are freed on return: wait for the kernel
+        if (dmrgdev::sync(e.dev())) return e.fail(DMRG_ERR_DEVICE, dmrgdev::last_error(e.dev()));
+        return DMRG_OK;
+    }
+};
+
+// --------------------------------------------------------------- reach
+Engine::Reach Engine::make_reach(int a, int b) const {
+    Reach r;
+    int maxm = 0;
+    for (int i = 0; i < N_; ++i) maxm += std::abs(tm0_.empty() ? 0 : delta_[i].tm);
+    r.off = maxm;
+    r.width = 2 * maxm + 1;
+    int cp = 0, cn = 0;
+    for (int i = a; i < b; ++i) (delta_[i].np ? cp : cn)++;
+    r.p.assign(cp + 1, std::vector<char>(r.width, 0));
+    r.n.assign(cn + 1, std::vector<char>(r.width, 0));
+    r.p[0][r.off] = 1;
+    r.n[0][r.off] = 1;
+    int kp = 0, kn = 0;
+    for (int i = a; i < b; ++i) {
+        auto& tab = delta_[i].np ? r.p : r.n;
+        int& k = delta_[i].np ? kp : kn;
+        int m = delta_[i].tm;
+        for (int c = k; c >= 0; --c)
+            for (int t = 0; t < r.width; ++t)
+                if (tab[c][t] && t + m >= 0 && t + m < r.width) tab[c + 1][t + m] = 1;
+        ++k;
+    }
+    return r;
+}
+
+bool Engine::reachable(const Reach& r, const QN& q) const {
+    if (q.np < 0 || q.nn < 0 || q.np >= (int)r.p.size() || q.nn >= (int)r.n.size()) return false;
+    const auto& P = r.p[q.np];
+    const auto& Nn = r.n[q.nn];
+    for (int tp = 0; tp < r.width; ++tp) {
+        if (!P[tp]) continue;
+        int tn = q.tm - (tp - r.off) + r.off;
+        if (tn >= 0 && tn < r.width && Nn[tn]) return true;
+    }
+    return false;
+}
+
+// --------------------------------------------------------------- loading
+dmrg_status Engine::load(int n, const int32_t* species, const int32_t* two_m, const double* eps,
+                         const double* V, int n_p, int n_n, int two_M) {
+    if (n < 1 || n > 64 || !species || !two_m || !eps || !V)
+        return fail(DMRG_ERR_ARG, "n_sites must be in 1..64 and all arrays non-null");
+    cur_.reset();
+    L_.clear();
+    R_.clear();
+    psi_.reset();
+    init_ = false;
+    loaded_ = false;
+    have_energy_ = false;
+    sweeps_done_ = 0;
+    for (int i = 0; i < n; ++i) {
+        if (species[i] != 0 && species[i] != 1) return fail(DMRG_ERR_ARG, "species must be 0 or 1");
+        if (!std::isfinite(eps[i])) return fail(DMRG_ERR_HAMILTONIAN, "eps is not finite");
+    }
+    size_t n4 = (size_t)n * n * n * n;
+    double vmax = 0.0;
+    for (size_t x = 0; x < n4; ++x) {
+        if (!std::isfinite(V[x])) return fail(DMRG_ERR_HAMILTONIAN, "V is not finite");
+        vmax = std::max(vmax, std::fabs(V[x]));
+    }
+    double tol = 1e-12 * std::max(vmax, 1e-300);
+    auto at = [&](int i, int j, int k, int l) { return V[(((size_t)i * n + j) * n + k) * n + l]; };
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j)
+            for (int k = 0; k < n; ++k)
+                for (int l = 0; l < n; ++l) {
+                    double v = at(i, j, k, l);
+                    bool bad = std::fabs(v + at(j, i, k, l)) > tol || std::fabs(v + at(i, j, l, k)) > tol ||
+                               std::fabs(v - at(k, l, i, j)) > tol;
+                    const char* why = "antisymmetry / (ij)<->(kl) symmetry";
+                    if (!bad && std::fabs(v) > tol) {
+                        bool mok = two_m[i] + two_m[j] == two_m[k] + two_m[l];
+                        int a = species[i] + species[j], b = species[k] + species[l];
+                        if (!mok || a != b) {
+                            bad = true;
+                            why = "selection rule (2M or charge not conserved)";
+                        }
+                    }
+                    if (bad) {
+                        std::ostringstream s;
+                        s << "V violates " << why << " at (i,j,k,l) = (" << i << "," << j << "," << k
+                          << "," << l << ")";
+                        return fail(DMRG_ERR_HAMILTONIAN, s.str());
+                    }
+                }
+    N_ = n;
+    sp0_.assign(species, species + n);
+    tm0_.assign(two_m, two_m + n);
+    eps0_.assign(eps, eps + n);
+    V0_.assign(V, V + n4);
+    T_ = QN(n_p, n_n, two_M);
+    // target reachable from all sites?
+    order_.clear();
+    delta_.assign(n, QN());
+    for (int i = 0; i < n; ++i) delta_[i] = species[i] == 0 ? QN(1, 0, two_m[i]) : QN(0, 1, two_m[i]);
+    Reach all = make_reach(0, n);
+    if (!reachable(all, T_)) return fail(DMRG_ERR_TARGET, "target (n_p, n_n, 2M) is not reachable");
+    loaded_ = true;
+    return DMRG_OK;
+}
+
+dmrg_status Engine::set_order(const int32_t* ordering) {
+    std::vector<int> ord(N_);
+    if (ordering) {
+        std::vector<char> seen(N_, 0);
+        for (int i = 0; i < N_; ++i) {
+            int s = ordering[i];
+            if (s < 0 || s >= N_ || seen[s]) return fail(DMRG_ERR_ARG, "ordering is not a permutation");
+            seen[s] = 1;
+            ord[i] = s;
+        }
+    } else {
+        std::iota(ord.begin(), ord.end(), 0);
+    }
+    if (init_ && ord == order_) return DMRG_OK;
+    order_ = ord;
+    eps_.assign(N_, 0.0);
+    V_.assign((size_t)N_ * N_ * N_ * N_, 0.0);
+    delta_.assign(N_, QN());
+    for (int a = 0; a < N_; ++a) {
+        int s = ord[a];
+        eps_[a] = eps0_[s];
+        delta_[a] = sp0_[s] == 0 ? QN(1, 0, tm0_[s]) : QN(0, 1, tm0_[s]);
+    }
+    for (int a = 0; a < N_; ++a)
+        for (int b = 0; b < N_; ++b)
+            for (int c = 0; c < N_; ++c)
+                for (int d = 0; d < N_; ++d)
+                    V_[(((size_t)a * N_ + b) * N_ + c) * N_ + d] =
+                        V0_[(((size_t)ord[a] * N_ + ord[b]) * N_ + ord[c]) * N_ + ord[d]];
+    pre_.clear();
+    for (int b = 0; b <= N_; ++b) pre_.push_back(make_reach(0, b));
+    init_ = false;
+    return DMRG_OK;
+}
+
+std::unique_ptr<Stored> Engine::vacuum(char side, int lo) {
+    auto v = std::make_unique<Stored>();
+    v->side = side;
+    v->lo = lo;
+    v->hi = lo;
+    v->normal = true;
+    v->basis.add(QN(), 1);
+    Op h;
+    h.dq = QN();
+    h.par = 0;
+    h.blk.push_back({0, 0, v->ops.alloc_block(1, 1), 1, 1});
+    h.index();
+    v->ops.add({'H', 0, 0}, std::move(h));
+    if (alloc_buf(v->ops.pool, v->ops.size * sizeof(double))) return nullptr;
+    if (dmrgdev::fill(dev_, v->ops.pool.d(), v->ops.size, 0.0)) return nullptr;
+    v->has_cfg = true;
+    v->cfg.push_back({0});
+    return v;
+}
+
+// ============================================================== blocking
+// A blocked operator is sum_terms (sum_refs coef * op_ref(base)) x site_op.
+enum SiteOp { S_I = 0, S_CD = 1, S_C = 2, S_N = 3 };
+static int site_par(int s) { return (s == S_CD || s == S_C) ? 1 : 0; }
+static int site_dsig(int s) { return s == S_CD ? 1 : (s == S_C ? -1 : 0); }
+// nonzero (sigma_out, sigma_in) elements with value 1
+static std::vector<std::pair<int, int>> site_elems(int s) {
+    switch (s) {
+        case S_I: return {{0, 0}, {1, 1}};
+        case S_CD: return {{1, 0}};
+        case S_C: return {{0, 1}};
+        default: return {{1, 1}};
+    }
+}
+struct Ref {
+    int op;        // index into the base op set
+    bool trans;
+    double coef;
+};
+struct FTerm {
+    int site;
+    bool ident = false;     // base part is the identity (times icoef)
+    double icoef = 0.0;
+    std::vector<Ref> refs;
+};
+using Formula = std::vector<FTerm>;
+
+struct Lin {
+    std::vector<Ref> refs;
+};
+
+// helpers returning a base-block operator (or a combination of them)
+struct FormulaCtx {
+    const Engine& e;
+    const Stored& B;
+    void add(Lin& l, const Key& k, double c, bool tr) const {
+        if (c == 0.0) return;
+        int x = B.ops.find(k);
+        if (x >= 0) l.refs.push_back({x, tr, c});
+    }
+    Lin one(const Key& k, double c = 1.0, bool tr = false) const {
+        Lin l;
+        add(l, k, c, tr);
+        return l;
+    }
+    // P^L_kl = sum_{i<j in L} V_ijkl c+_i c+_j
+    Lin PL(int k, int l) const {
+        Lin r;
+        if (!B.normal) return one({'P', k, l});
+        for (int i = B.lo; i < B.hi; ++i)
+            for (int j = i + 1; j < B.hi; ++j) add(r, {'A', i, j}, e.V(i, j, k, l), false);
+        return r;
+    }
+    // Q^L_jl = sum_{i,k in L} V_ijkl c+_i c_k
+    Lin QL(int j, int l) const {
+        Lin r;
+        if (!B.normal) return j <= l ? one({'Q', j, l}) : one({'Q', l, j}, 1.0, true);
+        for (int i = B.lo; i < B.hi; ++i)
+            for (int k = B.lo; k < B.hi; ++k) {
+                if (i <= k) add(r, {'B', i, k}, e.V(i, j, k, l), false);
+                else add(r, {'B', k, i}, e.V(i, j, k, l), true);
+            }
+        return r;
+    }
+    // P^R_ij = sum_{k<l in R} V_ijkl c_l c_k
+    Lin PR(int i, int j) const {
+        Lin r;
+        if (!B.normal) return one({'P', i, j});
+        for (int k = B.lo; k < B.hi; ++k)
+            for (int l = k + 1; l < B.hi; ++l) add(r, {'A', k, l}, e.V(i, j, k, l), true);
+        return r;
+    }
+    // Q^R_ik = sum_{j,l in R} V_ijkl c+_j c_l
+    Lin QR(int i, int k) const {
+        Lin r;
+        if (!B.normal) return i <= k ? one({'Q', i, k}) : one({'Q', k, i}, 1.0, true);
+        for (int j = B.lo; j < B.hi; ++j)
+            for (int l = B.lo; l < B.hi; ++l) {
+                if (j <= l) add(r, {'B', j, l}, e.V(i, j, k, l), false);
+                else add(r, {'B', l, j}, e.V(i, j, k, l), true);
+            }
+        return r;
+    }
+};
+
+static void push(Formula& f, int site, const Lin& l, double scale = 1.0) {
+    if (l.refs.empty()) return;
+    FTerm t;
+    t.site = site;
+    for (auto r : l.refs) {
+        r.coef *= scale;
+        t.refs.push_back(r);
+    }
+    f.push_back(std::move(t));
+}
+static void push_ident(Formula& f, int site, double c) {
+    if (c == 0.0) return;
+    FTerm t;
+    t.site = site;
+    t.ident = true;
+    t.icoef = c;
+    f.push_back(std::move(t));
+}
+
+// formulas for S = L * s (s = L.hi) at bond s
+static std::vector<std::pair<Key, Formula>> left_formulas(const Engine& e, const Stored& L) {
+    FormulaCtx F{e, L};
+    const int s = L.hi, N = e.N();
+    std::vector<std::pair<Key, Formula>> out;
+    // H_S = H_L + eps_s n_s + Q^L_ss n_s + R^L_s c_s + (R^L_s c_s)^+,
+    // (R c_s)^+ = c+_s R^+ = -R^+ c+_s
+    {
+        Formula f;
+        push(f, S_I, F.one({'H', 0, 0}));
+        push_ident(f, S_N, e.eps(s));
+        push(f, S_N, F.QL(s, s));
+        push(f, S_C, F.one({'R', s, 0}));
+        push(f, S_CD, F.one({'R', s, 0}, -1.0, true));
+        out.push_back({{'H', 0, 0}, f});
+    }
+    for (int i = L.lo; i < L.hi; ++i) {
+        Formula f;
+        push(f, S_I, F.one({'C', i, 0}));
+        out.push_back({{'C', i, 0}, f});
+    }
+    {
+        Formula f;
+        push_ident(f, S_CD, 1.0);
+        out.push_back({{'C', s, 0}, f});
+    }
+    // R^S_l = R^L_l + Q^L_sl c+_s - P^L_sl c_s - (sum_i V_issl c+_i) n_s
+    for (int l = s + 1; l < N; ++l) {
+        Formula f;
+        push(f, S_I, F.one({'R', l, 0}));
+        push(f, S_CD, F.QL(s, l));
+        push(f, S_C, F.PL(s, l), -1.0);
+        Lin cn;
+        for (int i = L.lo; i < L.hi; ++i) F.add(cn, {'C', i, 0}, -e.V(i, s, s, l), false);
+        push(f, S_N, cn);
+        out.push_back({{'R', l, 0}, f});
+    }
+    if (e.normal_S(s)) {
+        for (int i = L.lo; i < L.hi; ++i) {
+            for (int j = i + 1; j < L.hi; ++j) {
+                Formula f;
+                push(f, S_I, F.one({'A', i, j}));
+                out.push_back({{'A', i, j}, f});
+            }
+            Formula fa;
+            push(fa, S_CD, F.one({'C', i, 0}));
+            out.push_back({{'A', i, s}, fa});
+            for (int k = i; k < L.hi; ++k) {
+                Formula f;
+                push(f, S_I, F.one({'B', i, k}));
+                out.push_back({{'B', i, k}, f});
+            }
+            Formula fb;
+            push(fb, S_C, F.one({'C', i, 0}));
+            out.push_back({{'B', i, s}, fb});
+        }
+        Formula f;
+        push_ident(f, S_N, 1.0);
+        out.push_back({{'B', s, s}, f});
+    } else {
+        for (int k = s + 1; k < N; ++k)
+            for (int l = k + 1; l < N; ++l) {
+                // P^S_kl = P^L_kl + sum_i V_iskl c+_i c+_s
+                Formula f;
+                push(f, S_I, F.PL(k, l));
+                Lin cs;
+                for (int i = L.lo; i < L.hi; ++i) F.add(cs, {'C', i, 0}, e.V(i, s, k, l), false);
+                push(f, S_CD, cs);
+                out.push_back({{'P', k, l}, f});
+            }
+        for (int j = s + 1; j < N; ++j)
+            for (int l = j; l < N; ++l) {
+                // Q^S_jl = Q^L_jl + sum_i V_ijsl c+_i c_s - sum_k V_sjkl c_k^+.. c+_s + V_sjsl n_s
+                Formula f;
+                push(f, S_I, F.QL(j, l));
+                Lin a, b;
+                for (int i = L.lo; i < L.hi; ++i) F.add(a, {'C', i, 0}, e.V(i, j, s, l), false);
+                for (int k = L.lo; k < L.hi; ++k) F.add(b, {'C', k, 0}, -e.V(s, j, k, l), true);
+                push(f, S_C, a);
+                push(f, S_CD, b);
+                push_ident(f, S_N, e.V(s, j, s, l));
+                out.push_back({{'Q', j, l}, f});
+            }
+    }
+    return out;
+}
+
+// formulas for E = s * R (s = R.lo - 1) at bond s - 1
+static std::vector<std::pair<Key, Formula>> right_formulas(const Engine& e, const Stored& R) {
+    FormulaCtx F{e, R};
+    const int s = R.lo - 1;
+    std::vector<std::pair<Key, Formula>> out;
+    // H_E = H_R + eps_s n_s + n_s Q^R_ss + c+_s R^R_s + (c+_s R^R_s)^+,
+    // (c+_s R)^+ = R^+ c_s = -c_s R^+
+    {
+        Formula f;
+        push(f, S_I, F.one({'H', 0, 0}));
+        push_ident(f, S_N, e.eps(s));
+        push(f, S_N, F.QR(s, s));
+        push(f, S_CD, F.one({'R', s, 0}));
+        push(f, S_C, F.one({'R', s, 0}, -1.0, true));
+        out.push_back({{'H', 0, 0}, f});
+    }
+    {
+        Formula f;
+        push_ident(f, S_CD, 1.0);
+        out.push_back({{'C', s, 0}, f});
+    }
+    for (int j = R.lo; j < R.hi; ++j) {
+        Formula f;
+        push(f, S_I, F.one({'C', j, 0}));
+        out.push_back({{'C', j, 0}, f});
+    }
+    // R^E_i = R^R_i + c+_s P^R_is + c_s Q^R_is - n_s sum_l V_issl c_l
+    for (int i = 0; i < s; ++i) {
+        Formula f;
+        push(f, S_I, F.one({'R', i, 0}));
+        push(f, S_CD, F.PR(i, s));
+        push(f, S_C, F.QR(i, s));
+        Lin cn;
+        for (int l = R.lo; l < R.hi; ++l) F.add(cn, {'C', l, 0}, -e.V(i, s, s, l), true);
+        push(f, S_N, cn);
+        out.push_back({{'R', i, 0}, f});
+    }
+    if (!e.normal_S(s - 1)) {
+        for (int l = R.lo; l < R.hi; ++l) {
+            Formula fa, fb;
+            push(fa, S_CD, F.one({'C', l, 0}));
+            push(fb, S_CD, F.one({'C', l, 0}, 1.0, true));
+            out.push_back({{'A', s, l}, fa});
+            out.push_back({{'B', s, l}, fb});
+        }
+        for (int k = R.lo; k < R.hi; ++k) {
+            for (int l = k + 1; l < R.hi; ++l) {
+                Formula f;
+                push(f, S_I, F.one({'A', k, l}));
+                out.push_back({{'A', k, l}, f});
+            }
+            for (int l = k; l < R.hi; ++l) {
+                Formula f;
+                push(f, S_I, F.one({'B', k, l}));
+                out.push_back({{'B', k, l}, f});
+            }
+        }
+        Formula f;
+        push_ident(f, S_N, 1.0);
+        out.push_back({{'B', s, s}, f});
+    } else {
+        for (int i = 0; i < s; ++i)
+            for (int j = i + 1; j < s; ++j) {
+                // P^E_ij = P^R_ij - sum_l V_ijsl c_s c_l
+                Formula f;
+                push(f, S_I, F.PR(i, j));
+                Lin cl;
+                for (int l = R.lo; l < R.hi; ++l) F.add(cl, {'C', l, 0}, -e.V(i, j, s, l), true);
+                push(f, S_C, cl);
+                out.push_back({{'P', i, j}, f});
+            }
+        for (int i = 0; i < s; ++i)
+            for (int k = i; k < s; ++k) {
+                // Q^E_ik = Q^R_ik + V_isks n_s + sum_l V_iskl c+_s c_l - sum_j V_ijks c_s c+_j
+                Formula f;
+                push(f, S_I, F.QR(i, k));
+                push_ident(f, S_N, e.V(i, s, k, s));
+                Lin a, b;
+                for (int l = R.lo; l < R.hi; ++l) F.add(a, {'C', l, 0}, e.V(i, s, k, l), true);
+                for (int j = R.lo; j < R.hi; ++j) F.add(b, {'C', j, 0}, -e.V(i, j, k, s), false);
+                push(f, S_CD, a);
+                push(f, S_C, b);
+                out.push_back({{'Q', i, k}, f});
+            }
+    }
+    return out;
+}
+
+// Build the enlarged block (sub-sectors of base sectors x site occupation),
+// keeping merged sectors whose quantum numbers are in `allowed` (sorted), and
+// its operators from the formulas, executed as scaled block copies.
+dmrg_status Engine::enlarge(const Stored& base, char side, const std::vector<QN>& allowed, Enl& en,
+                            OpSet& ops) {
+    const int s = side == 'L' ? base.hi : base.lo - 1;
+    en = Enl();
+    en.side = side;
+    en.site = s;
+    en.dsite = delta_[s];
+    std::set<QN> allow(allowed.begin(), allowed.end());
+    std::map<QN, std::array<int, 2>> parts;   // merged q -> base sector per sigma
+    for (int sg = 0; sg < 2; ++sg)
+        for (size_t b = 0; b < base.basis.q.size(); ++b) {
+            QN q = sg ? base.basis.q[b] + delta_[s] : base.basis.q[b];
+            if (!allow.count(q)) continue;
+            auto it = parts.find(q);
+            if (it == parts.end()) it = parts.insert({q, {-1, -1}}).first;
+            it->second[sg] = (int)b;
+        }
+    for (auto& kv : parts) {
+        int m = (int)en.mq.size();
+        en.midx[kv.first] = m;
+        en.mq.push_back(kv.first);
+        std::array<int, 2> ms = {-1, -1};
+        int off = 0;
+        for (int sg = 0; sg < 2; ++sg) {
+            int b = kv.second[sg];
+            if (b < 0) continue;
+            Sub sb{m, b, sg, off, base.basis.d[b], kv.first};
+            off += sb.dim;
+            ms[sg] = (int)en.sub.size();
+            en.sub_of[{b, sg}] = (int)en.sub.size();
+            en.sub.push_back(sb);
+        }
+        en.md.push_back(off);
+        en.msub.push_back(ms);
+    }
+    // operators
+    auto formulas = side == 'L' ? left_formulas(*this, base) : right_formulas(*this, base);
+    ops = OpSet();
+    LB lb;
+    for (auto& kf : formulas) {
+        const Formula& f = kf.second;
+        if (f.empty()) continue;
+        // dq and parity from the first term
+        QN bdq;
+        int bpar = 0;
+        const FTerm& t0 = f[0];
+        if (!t0.ident) {
+            const Op& o = base.ops.ops[t0.refs[0].op];
+            bdq = t0.refs[0].trans ? -o.dq : o.dq;
+            bpar = o.par;
+        }
+        int ds = site_dsig(t0.site);
+        QN dq = ds == 1 ? bdq + delta_[s] : (ds == -1 ? bdq - delta_[s] : bdq);
+        int par = (bpar + site_par(t0.site)) % 2;
+        // contributions per (out sub, in sub)
+        std::map<std::pair<int, int>, std::vector<LcTerm>> contrib;
+        for (const FTerm& t : f) {
+            int tpar = 0;
+            if (!t.ident) tpar = base.ops.ops[t.refs[0].op].par;
+            for (size_t i_in = 0; i_in < en.sub.size(); ++i_in) {
+                const Sub& si = en.sub[i_in];
+                for (auto el : site_elems(t.site)) {
+                    if (el.second != si.sigma) continue;
+                    double sign;
+                    if (side == 'L') sign = (site_par(t.site) && (base.basis.q[si.base].n() & 1)) ? -1.0 : 1.0;
+                    else sign = (tpar && si.sigma) ? -1.0 : 1.0;
+                    if (t.ident) {
+                        int i_out = en.find_sub(si.base, el.first);
+                        if (i_out < 0) continue;
+                        LcTerm lt{};
+                        lt.coef = t.icoef * sign;
+                        lt.ident = 1;
+                        contrib[{i_out, (int)i_in}].push_back(lt);
+                        continue;
+                    }
+                    for (const Ref& r : t.refs) {
+                        const Op& o = base.ops.ops[r.op];
+                        const Blk* bk = r.trans ? o.out_blk(si.base) : o.in_blk(si.base);
+                        if (!bk) continue;
+                        int b_out = r.trans ? bk->in : bk->out;
+                        int i_out = en.find_sub(b_out, el.first);
+                        if (i_out < 0) continue;
+                        LcTerm lt{};
+                        lt.coef = r.coef * sign;
+                        lt.src_off = bk->off;
+                        lt.ld = bk->cols;
+                        lt.trans = r.trans;
+                        lt.buf = 0;
+                        contrib[{i_out, (int)i_in}].push_back(lt);
+                    }
+                }
+            }
+        }
+        if (contrib.empty()) continue;
+        Op op;
+        op.dq = dq;
+        op.par = par;
+        for (auto& c : contrib) {
+            const Sub& so = en.sub[c.first.first];
+            const Sub& si = en.sub[c.first.second];
+            if (so.q != si.q + dq) return fail(DMRG_ERR_DEVICE, "internal: inconsistent blocking formula");
+            Blk bk{c.first.first, c.first.second, ops.alloc_block(so.dim, si.dim), so.dim, si.dim};
+            op.blk.push_back(bk);
+            lb.block(1, bk.off, bk.rows, bk.cols, c.second);
+        }
+        op.index();
+        ops.add(kf.first, std::move(op));
+    }
+    TRY(alloc_buf(ops.pool, std::max<int64_t>(ops.size, 1) * sizeof(double)));
+    double* bufs[2] = {base.ops.pool.d(), ops.pool.d()};
+    TRY(lb.run(*this, bufs));
+    return DMRG_OK;
+}
+
+// ====================================================== renormalisation
+// New stored block from an enlarged block: kept merged sectors keep_m with
+// kdim states; U (iso, comp_dim x k per kept sector) must already be in out.iso.
+// O'[x', x] = U_{x'}^T O[x', x] U_x summed over the sub-sector blocks.
+dmrg_status Engine::renormalize(const Enl& en, const OpSet& ops, bool normal_in, Stored& out,
+                                const std::vector<int>& keep_m, const std::vector<int>& kdim) {
+    std::vector<int> newidx(en.mq.size(), -1);
+    for (size_t x = 0; x < keep_m.size(); ++x) newidx[keep_m[x]] = (int)x;
+    // transition from normal to complementary pair operators?
+    bool need_normal = out.side == 'L' ? left_normal(out.length()) : right_normal(out.lo);
+    bool transition = normal_in && !need_normal;
+    out.normal = normal_in && need_normal;
+    OpSet tmp;   // renormalised A, B at the transition
+    GB g1, g2;
+    int64_t t_elems = 0;
+    struct Pending {
+        int which;   // 0 = out.ops, 1 = tmp
+        Key key;
+        Op op;
+    };
+    std::vector<Pending> pend;
+    for (size_t o = 0; o < ops.ops.size(); ++o) {
+        const Key& key = ops.keys[o];
+        const Op& op = ops.ops[o];
+        bool to_tmp = transition && (key.k == 'A' || key.k == 'B');
+        OpSet& dst = to_tmp ? tmp : out.ops;
+        // group blocks by (m_out, m_in)
+        std::map<std::pair<int, int>, std::vector<const Blk*>> groups;
+        for (const Blk& b : op.blk) {
+            int mo = en.sub[b.out].m, mi = en.sub[b.in].m;
+            if (newidx[mo] < 0 || newidx[mi] < 0) continue;
+            groups[{mo, mi}].push_back(&b);
+        }
+        if (groups.empty()) continue;
+        Op nop;
+        nop.dq = op.dq;
+        nop.par = op.par;
+        for (auto& gkv : groups) {
+            int mo = gkv.first.first, mi = gkv.first.second;
+            int xo = newidx[mo], xi = newidx[mi];
+            int ko = kdim[xo], ki = kdim[xi];
+            Blk nb{xo, xi, dst.alloc_block(ko, ki), ko, ki};
+            // phase 1: T[(i_out)] = sum_{i_in} O[i_out, i_in] U_mi[rows i_in]  (d(i_out) x ki)
+            std::map<int, std::vector<const Blk*>> by_out;
+            for (const Blk* b : gkv.second) by_out[b->out].push_back(b);
+            g2.begin();
+            for (auto& bo : by_out) {
+                const Sub& so = en.sub[bo.first];
+                int64_t toff = t_elems;
+                t_elems += ((int64_t)so.dim * ki + 31) / 32 * 32;
+                g1.begin();
+                for (const Blk* b : bo.second) {
+                    const Sub& si = en.sub[b->in];
+                    g1.chunk(1.0, 0, b->off, b->cols, false, 1, out.iso_off[xi] + (int64_t)si.off * ki, ki,
+                             false, si.dim);
+                }
+                g1.end(2, toff, ki, so.dim, ki, 0);
+                // phase 2 chunk: U_mo[rows i_out]^T T
+                g2.chunk(1.0, 1, out.iso_off[xo] + (int64_t)so.off * ko, ko, true, 2, toff, ki, false, so.dim);
+            }
+            g2.end(to_tmp ? 4 : 3, nb.off, ki, ko, ki, 0);
+            nop.blk.push_back(nb);
+        }
+        nop.index();
+        pend.push_back({to_tmp ? 1 : 0, key, std::move(nop)});
+    }
+    for (auto& p : pend) (p.which ? tmp : out.ops).add(p.key, std::move(p.op));
+    // device execution
+    TRY(alloc_buf(out.ops.pool, std::max<int64_t>(out.ops.size, 1) * sizeof(double)));
+    if (tmp.size) TRY(alloc_buf(tmp.pool, tmp.size * sizeof(double)));
+    Buf tbuf;
+    TRY(alloc_buf(tbuf, std::max<int64_t>(t_elems, 1) * sizeof(double)));
+    GemmPlan p1, p2;
+    TRY(finish_plan(*this, g1, p1));
+    TRY(finish_plan(*this, g2, p2));
+    void* bufs[5] = {ops.pool.p, out.iso.p, tbuf.p, out.ops.pool.p, tmp.pool.p};
+    TRY(run_gemm(dmrgdev::P_F64, bufs, p1));
+    TRY(run_gemm(dmrgdev::P_F64, bufs, p2));
+    DEV(dmrgdev::sync(dev_));
+    if (!transition) return DMRG_OK;
+    // complementary operators of the new block from its renormalised normal ones
+    FormulaCtx F{*this, out};
+    struct Item {
+        Key key;
+        Lin lin;
+    };
+    std::vector<Item> items;
+    // helper view: resolve refs against tmp
+    auto addk = [&](Lin& l, const Key& k, double c, bool tr) {
+        if (c == 0.0) return;
+        int x = tmp.find(k);
+        if (x >= 0) l.refs.push_back({x, tr, c});
+    };
+    if (out.side == 'L') {
+        for (int k = out.hi; k < N_; ++k)
+            for (int l = k + 1; l < N_; ++l) {
+                Lin lin;
+                for (int i = out.lo; i < out.hi; ++i)
+                    for (int j = i + 1; j < out.hi; ++j) addk(lin, {'A', i, j}, V(i, j, k, l), false);
+                items.push_back({{'P', k, l}, lin});
+            }
+        for (int j = out.hi; j < N_; ++j)
+            for (int l = j; l < N_; ++l) {
+                Lin lin;
+                for (int i = out.lo; i < out.hi; ++i)
+                    for (int k = out.lo; k < out.hi; ++k) {
+                        if (i <= k) addk(lin, {'B', i, k}, V(i, j, k, l), false);
+                        else addk(lin, {'B', k, i}, V(i, j, k, l), true);
+                    }
+                items.push_back({{'Q', j, l}, lin});
+            }
+    } else {
+        for (int i = 0; i < out.lo; ++i)
+            for (int j = i + 1; j < out.lo; ++j) {
+                Lin lin;
+                for (int k = out.lo; k < out.hi; ++k)
+                    for (int l = k + 1; l < out.hi; ++l) addk(lin, {'A', k, l}, V(i, j, k, l), true);
+                items.push_back({{'P', i, j}, lin});
+            }
+        for (int i = 0; i < out.lo; ++i)
+            for (int k = i; k < out.lo; ++k) {
+                Lin lin;
+                for (int j = out.lo; j < out.hi; ++j)
+                    for (int l = out.lo; l < out.hi; ++l) {
+                        if (j <= l) addk(lin, {'B', j, l}, V(i, j, k, l), false);
+                        else addk(lin, {'B', l, j}, V(i, j, k, l), true);
+                    }
+                items.push_back({{'Q', i, k}, lin});
+            }
+    }
+    (void)F;
+    // new pool = old pool content + complementary ops
+    OpSet comp;
+    LB lb;
+    std::vector<std::pair<Key, Op>> newops;
+    for (auto& it : items) {
+        if (it.lin.refs.empty()) continue;
+        std::map<int, std::vector<LcTerm>> by_in;   // input sector -> terms
+        std::map<int, int> out_of;
+        QN dq;
+        int par = 0;
+        bool first = true;
+        for (const Ref& r : it.lin.refs) {
+            const Op& o = tmp.ops[r.op];
+            QN odq = r.trans ? -o.dq : o.dq;
+            if (first) {
+                dq = odq;
+                par = o.par;
+                first = false;
+            }
+            for (const Blk& b : o.blk) {
+                int in = r.trans ? b.out : b.in, ot = r.trans ? b.in : b.out;
+                LcTerm lt{};
+                lt.coef = r.coef;
+                lt.src_off = b.off;
+                lt.ld = b.cols;
+                lt.trans = r.trans;
+                lt.buf = 0;
+                by_in[in].push_back(lt);
+                out_of[in] = ot;
+            }
+        }
+        Op op;
+        op.dq = dq;
+        op.par = par;
+        for (auto& kv : by_in) {
+            int in = kv.first, ot = out_of[in];
+            Blk nb{ot, in, out.ops.size + comp.alloc_block(kdim[ot], kdim[in]), kdim[ot], kdim[in]};
+            op.blk.push_back(nb);
+            lb.block(1, nb.off - out.ops.size, nb.rows, nb.cols, kv.second);
+        }
+        op.index();
+        newops.push_back({it.key, std::move(op)});
+    }
+    // grow the pool: copy the renormalised part, then the combinations
+    Buf np;
+    TRY(alloc_buf(np, std::max<int64_t>(out.ops.size + comp.size, 1) * sizeof(double)));
+    DEV(dmrgdev::d2d(dev_, np.p, out.ops.pool.p, out.ops.size * sizeof(double)));
+    double* bufs2[2] = {tmp.pool.d(), np.d() + out.ops.size};
+    TRY(lb.run(*this, bufs2));
+    out.ops.size += comp.size;
+    out.ops.pool = std::move(np);
+    for (auto& kv : newops) out.ops.add(kv.first, std::move(kv.second));
+    return DMRG_OK;
+}
+
+// =============================================================== bonds
+dmrg_status Engine::setup_bond(int b, std::unique_ptr<Bond>& outp) {
+    double t0 = now();
+    auto B = std::make_unique<Bond>();
+    B->b = b;
+    const Stored& L = *L_[b];
+    const Stored& R = *R_[b + 2];
+    // E sectors: complementable by the sites 0..b
+    std::vector<QN> eq;
+    {
+        std::set<QN> cand;
+        for (int sg = 0; sg < 2; ++sg)
+            for (const QN& q : R.basis.q) cand.insert(sg ? q + delta_[b + 1] : q);
+        for (const QN& q : cand)
+            if (reachable(pre_[b + 1], T_ - q)) eq.push_back(q);
+    }
+    // S sectors: partner in E; then E sectors: partner in S
+    std::vector<QN> sq;
+    {
+        std::set<QN> es(eq.begin(), eq.end()), cand;
+        for (int sg = 0; sg < 2; ++sg)
+            for (const QN& q : L.basis.q) cand.insert(sg ? q + delta_[b] : q);
+        for (const QN& q : cand)
+            if (es.count(T_ - q)) sq.push_back(q);
+        std::set<QN> ss(sq.begin(), sq.end());
+        std::vector<QN> eq2;
+        for (const QN& q : eq)
+            if (ss.count(T_ - q)) eq2.push_back(q);
+        eq.swap(eq2);
+    }
+    TRY(enlarge(L, 'L', sq, B->S, B->Sops));
+    TRY(enlarge(R, 'R', eq, B->E, B->Eops));
+    // psi layout: merged S sectors in order
+    B->blk_of_S.assign(B->S.mq.size(), -1);
+    for (size_t m = 0; m < B->S.mq.size(); ++m) {
+        int me = B->E.find_m(T_ - B->S.mq[m]);
+        if (me < 0) continue;
+        B->blk_of_S[m] = (int)B->pm_S.size();
+        B->pm_S.push_back((int)m);
+        B->pm_E.push_back(me);
+        B->poff.push_back(B->dim);
+        B->dim += (int64_t)B->S.md[m] * B->E.md[me];
+    }
+    // H_eff terms of the S|E split of H: H_S, H_E; pair terms with the two-body sums
+    // carried by complementary operators of the larger side; the 3+1 and 1+3 terms
+    auto& T = B->terms;
+    const OpSet &So = B->Sops, &Eo = B->Eops;
+    T.push_back({1.0, So.find({'H', 0, 0}), -1, false, false, false, 0});
+    T.push_back({1.0, -1, Eo.find({'H', 0, 0}), false, false, false, 0});
+    auto pair = [&](const Key& ka, bool ta, const Key& kb, bool tb, int par, bool hc) {
+        int a = So.find(ka), c = Eo.find(kb);
+        if (a < 0 || c < 0) return;
+        T.push_back({1.0, a, c, ta, tb, false, par});
+        if (hc) T.push_back({1.0, a, c, !ta, !tb, true, par});
+    };
+    if (normal_S(b)) {
+        for (int i = 0; i <= b; ++i) {
+            for (int j = i + 1; j <= b; ++j) pair({'A', i, j}, false, {'P', i, j}, false, 0, true);
+            for (int k = i; k <= b; ++k) pair({'B', i, k}, false, {'Q', i, k}, false, 0, i < k);
+        }
+    } else {
+        for (int k = b + 1; k < N_; ++k) {
+            for (int l = k + 1; l < N_; ++l) pair({'P', k, l}, false, {'A', k, l}, true, 0, true);
+            for (int l = k; l < N_; ++l) pair({'Q', k, l}, false, {'B', k, l}, false, 0, k < l);
+        }
+    }
+    for (int l = b + 1; l < N_; ++l) pair({'R', l, 0}, false, {'C', l, 0}, true, 1, true);
+    for (int i = 0; i <= b; ++i) pair({'C', i, 0}, false, {'R', i, 0}, false, 1, true);
+    TRY(build_heff_plan(*B));
+    TRY(build_diag(*B));
+    acc_.blocking_seconds += now() - t0;
+    outp = std::move(B);
+    return DMRG_OK;
+}
+
+// Two launches per product: Z = psi_sub op(B)^T for every term with an E
+// operator, then every output sub-block accumulates op(A) Z (or psi op(B)^T,
+// or op(A) psi) over all its terms in one tile task (no atomics).  Terms are
+// grouped so that each group's Z fits the scratch budget; the first group
+// writes every output sub-block, later groups accumulate.
+// bufs: 0 S ops, 1 E ops, 2 x, 3 Z, 4 y.
+dmrg_status Engine::build_heff_plan(Bond& B) {
+    const Enl &S = B.S, &E = B.E;
+    const int nb = (int)B.pm_S.size();
+    auto subid = [&](int x, int i, int j) { return x * 4 + S.sub[i].sigma * 2 + E.sub[j].sigma; };
+    const int64_t zbudget =
+        opt_.scratch_bytes ? (int64_t)(opt_.scratch_bytes / sizeof(double)) : ((int64_t)1 << 31);
+    struct Out {
+        int x, i, j;
+    };
+    std::vector<Out> outs(nb * 4, Out{-1, -1, -1});
+    for (int x = 0; x < nb; ++x)
+        for (int i : S.msub[B.pm_S[x]])
+            for (int j : E.msub[B.pm_E[x]])
+                if (i >= 0 && j >= 0) outs[subid(x, i, j)] = {x, i, j};
+
+    // work of one term, Z offsets relative to the term's own Z
+    struct ZBlk {
+        int64_t xoff, boff, zoff;
+        int ldx, ldb, K, M, Nn;
+        bool btr;
+    };
+    struct TermWork {
+        std::vector<ZBlk> z;
+        std::vector<std::pair<int, GemmChunk>> c2;
+        int64_t zsize = 0;
+    };
+    auto work = [&](const Term& tm, TermWork& w) -> dmrg_status {
+        const Op* A = tm.a >= 0 ? &B.Sops.ops[tm.a] : nullptr;
+        const Op* Bo = tm.b >= 0 ? &B.Eops.ops[tm.b] : nullptr;
+        static const std::vector<int> one_none = {-1};
+        for (int x = 0; x < nb; ++x) {
+            const int mS = B.pm_S[x], mE = B.pm_E[x];
+            const int ldx = E.md[mE];
+            for (int i : S.msub[mS]) {
+                if (i < 0) continue;
+                for (int ai : A ? A->acting(i, tm.ta) : one_none) {
+                    const Blk* ab = ai >= 0 ? &A->blk[ai] : nullptr;
+                    const int i2 = ab ? (tm.ta ? ab->in : ab->out) : i;
+                    for (int j : E.msub[mE]) {
+                        if (j < 0) continue;
+                        for (int bi : Bo ? Bo->acting(j, tm.tb) : one_none) {
+                            const Blk* bb = bi >= 0 ? &Bo->blk[bi] : nullptr;
+                            const int j2 = bb ? (tm.tb ? bb->in : bb->out) : j;
+                            const int x2 = B.blk_of_S[S.sub[i2].m];
+                            if (x2 < 0 || B.pm_E[x2] != E.sub[j2].m)
+                                return fail(DMRG_ERR_DEVICE, "internal: H_eff term leaves the target sector");
+                            double sg = 1.0;
+                            if (tm.par) sg = ((tm.sign_out ? S.sub[i2].q.n() : S.sub[i].q.n()) & 1) ? -1.0 : 1.0;
+                            const double alpha = tm.coef * sg;
+                            const int64_t xoff = B.poff[x] + (int64_t)S.sub[i].off * ldx + E.sub[j].off;
+                            const int di = S.sub[i].dim, dj = E.sub[j].dim, dj2 = E.sub[j2].dim;
+                            GemmChunk c{};
+                            if (ab && bb) {
+                                const int64_t zo = w.zsize;
+                                w.zsize += ((int64_t)di * dj2 + 7) / 8 * 8;
+                                w.z.push_back({xoff, bb->off, zo, ldx, bb->cols, dj, di, dj2, !tm.tb});
+                                c = GemmChunk{alpha, ab->off, zo, ab->cols, dj2, di, 0, 3, (uint8_t)tm.ta, 0};
+                            } else if (ab) {
+                                c = GemmChunk{alpha, ab->off, xoff, ab->cols, ldx, di, 0, 2, (uint8_t)tm.ta, 0};
+                            } else if (bb) {
+                                c = GemmChunk{alpha, xoff, bb->off, ldx, bb->cols, dj, 2, 1, 0, (uint8_t)!tm.tb};
+                            } else {
+                                continue;
+                            }
+                            w.c2.push_back({subid(x2, i2, j2), c});
+                        }
+                    }
+                }
+            }
+        }
+        return DMRG_OK;
+    };
+
+    B.groups.clear();
+    B.flops = 0.0;
+    std::vector<std::vector<GemmChunk>> lists(nb * 4);
+    GB g1;
+    int64_t z = 0;
+    bool first = true;
+    auto close_group = [&]() -> dmrg_status {
+        HeffGroup grp;
+        grp.z_elems = z;
+        GB g2;
+        for (int id = 0; id < nb * 4; ++id) {
+            const Out& o = outs[id];
+            if (o.x < 0) continue;
+            auto& l = lists[id];
+            if (!first && l.empty()) continue;
+            g2.begin();
+            g2.chunks.insert(g2.chunks.end(), l.begin(), l.end());
+            const int ldy = E.md[B.pm_E[o.x]];
+            const int64_t yoff = B.poff[o.x] + (int64_t)S.sub[o.i].off * ldy + E.sub[o.j].off;
+            g2.end(4, yoff, ldy, S.sub[o.i].dim, E.sub[o.j].dim, first ? 0 : 1);
+            l.clear();
+        }
+#ifdef DMRG_DEBUG
+        for (auto& tk : g2.tasks) {
+            fprintf(stderr, "  P2 task c_off=%lld ldc=%d m0=%d n0=%d mt=%d nt=%d chunks %d..%d beta=%d\n", (long long)tk.c_off, tk.ldc, tk.m0, tk.n0, tk.mt, tk.nt, tk.chunk_begin, tk.chunk_end, tk.beta);
+            for (int c = tk.chunk_begin; c < tk.chunk_end; ++c) { auto& k = g2.chunks[c]; fprintf(stderr, "     ch a=%d:%lld lda=%d tr=%d b=%d:%lld ldb=%d tr=%d K=%d alpha=%g\n", k.a_buf, (long long)k.a_off, k.lda, k.a_trans, k.b_buf, (long long)k.b_off, k.ldb, k.b_trans, k.K, k.alpha); }
+        }
+#endif
+        TRY(finish_plan(*this, g1, grp.p1));
+        TRY(finish_plan(*this, g2, grp.p2));
+        B.flops += grp.p1.flops + grp.p2.flops;
+        B.groups.push_back(std::move(grp));
+        g1 = GB();
+        z = 0;
+        first = false;
+        return DMRG_OK;
+    };
+    for (const Term& tm : B.terms) {
+        TermWork w;
+        TRY(work(tm, w));
+        if (z > 0 && z + w.zsize > zbudget) TRY(close_group());
+        for (const ZBlk& zb : w.z) {
+            g1.begin();
+            g1.chunk(1.0, 2, zb.xoff, zb.ldx, false, 1, zb.boff, zb.ldb, zb.btr, zb.K);
+            g1.end(3, z + zb.zoff, zb.Nn, zb.M, zb.Nn, 0);
+        }
+        for (auto& pc : w.c2) {
+            GemmChunk c = pc.second;
+            if (c.b_buf == 3) c.b_off += z;
+            lists[pc.first].push_back(c);
+        }
+        z += w.zsize;
+    }
+    TRY(close_group());
+#ifdef DMRG_DEBUG
+    fprintf(stderr, "bond %d: %zu terms, %d psi blocks, dim %lld\n", B.b, B.terms.size(), nb, (long long)B.dim);
+    for (size_t t = 0; t < B.terms.size(); ++t) {
+        const Term& tm = B.terms[t];
+        fprintf(stderr, "  term %zu a=%d(%c%d,%d) ta=%d b=%d(%c%d,%d) tb=%d so=%d par=%d\n", t, tm.a,
+                tm.a >= 0 ? B.Sops.keys[tm.a].k : '-', tm.a >= 0 ? B.Sops.keys[tm.a].i : 0, tm.a >= 0 ? B.Sops.keys[tm.a].j : 0, tm.ta, tm.b,
+                tm.b >= 0 ? B.Eops.keys[tm.b].k : '-', tm.b >= 0 ? B.Eops.keys[tm.b].i : 0, tm.b >= 0 ? B.Eops.keys[tm.b].j : 0, tm.tb, tm.sign_out, tm.par);
+    }
+    for (size_t o = 0; o < B.Eops.ops.size(); ++o) {
+        fprintf(stderr, "  Eop %c%d,%d:", B.Eops.keys[o].k, B.Eops.keys[o].i, B.Eops.keys[o].j);
+        for (auto& b : B.Eops.ops[o].blk) fprintf(stderr, " (%d<-%d %dx%d)", b.out, b.in, b.rows, b.cols);
+        fprintf(stderr, "\n");
+    }
+    for (size_t j = 0; j < E.sub.size(); ++j) fprintf(stderr, "  Esub %zu m=%d base=%d sg=%d off=%d dim=%d\n", j, E.sub[j].m, E.sub[j].base, E.sub[j].sigma, E.sub[j].off, E.sub[j].dim);
+#endif
+    int64_t zmax = 0;
+    for (auto& g : B.groups) zmax = std::max(zmax, g.z_elems);
+    if ((int64_t)(z_.bytes / sizeof(double)) < zmax)
+        TRY(alloc_buf(z_, std::max<int64_t>(zmax, 1) * sizeof(double)));
+    return DMRG_OK;
+}
+
+dmrg_status Engine::build_diag(Bond& B) {
+    const Enl &S = B.S, &E = B.E;
+    std::vector<DiagTask> tasks;
+    std::vector<DiagTerm> terms;
+    for (size_t x = 0; x < B.pm_S.size(); ++x) {
+        int mS = B.pm_S[x], mE = B.pm_E[x];
+        int ld = E.md[mE];
+        for (int i : S.msub[mS]) {
+            if (i < 0) continue;
+            for (int j : E.msub[mE]) {
+                if (j < 0) continue;
+                int32_t t0 = (int32_t)terms.size();
+                for (const Term& tm : B.terms) {
+                    const Op* A = tm.a >= 0 ? &B.Sops.ops[tm.a] : nullptr;
+                    const Op* Bo = tm.b >= 0 ? &B.Eops.ops[tm.b] : nullptr;
+                    if ((A && A->dq != QN()) || (Bo && Bo->dq != QN())) continue;
+                    DiagTerm d{};
+                    d.coef = tm.coef;
+                    const Blk* ab = nullptr;
+                    const Blk* bb = nullptr;
+                    if (A)
+                        for (int q : A->ins(i))
+                            if (A->blk[q].out == i) ab = &A->blk[q];
+                    if (Bo)
+                        for (int q : Bo->ins(j))
+                            if (Bo->blk[q].out == j) bb = &Bo->blk[q];
+                    if (A) {
+                        if (!ab) continue;
+                        d.a_off = ab->off;
+                        d.a_step = ab->cols + 1;
+                        d.a_buf = 0;
+                    } else {
+                        d.a_ident = 1;
+                    }
+                    if (Bo) {
+                        if (!bb) continue;
+                        d.b_off = bb->off;
+                        d.b_step = bb->cols + 1;
+                        d.b_buf = 1;
+                    } else {
+                        d.b_ident = 1;
+                    }
+                    terms.push_back(d);
+                }
+                int32_t t1 = (int32_t)terms.size();
+                int rows = S.sub[i].dim, cols = E.sub[j].dim;
+                int64_t off = B.poff[x] + (int64_t)S.sub[i].off * ld + E.sub[j].off;
+                for (int r0 = 0; r0 < rows; r0 += 32)
+                    for (int c0 = 0; c0 < cols; c0 += 32)
+                        tasks.push_back({off, ld, r0, c0, std::min(32, rows - r0), std::min(32, cols - c0), t0, t1});
+            }
+        }
+    }
+    TRY(alloc_buf(B.diag, std::max<int64_t>(B.dim, 1) * sizeof(double)));
+    Buf dt, dterm;
+    TRY(upload(dt, tasks));
+    TRY(upload(dterm, terms));
+    double* bufs[3] = {B.Sops.pool.d(), B.Eops.pool.d(), B.diag.d()};
+    if (!tasks.empty()) DEV(dmrgdev::diag(dev_, bufs, dt.as<DiagTask>(), (int)tasks.size(), dterm.as<DiagTerm>()));
+    DEV(dmrgdev::sync(dev_));
+    return DMRG_OK;
+}
+
+dmrg_status Engine::ensure_lo(Bond& B, int prec) {
+    if (B.lo_prec == prec) return DMRG_OK;
+    for (OpSet* o : {&B.Sops, &B.Eops}) {
+        size_t es = prec == dmrgdev::P_F32 ? 4 : 2;
+        TRY(alloc_buf(o->pool_lo, std::max<int64_t>(o->size, 1) * es));
+        DEV(dmrgdev::convert(dev_, dmrgdev::P_F64, o->pool.p, prec, o->pool_lo.p, o->size));
+        o->lo_prec = prec;
+    }
+    B.lo_prec = prec;
+    return DMRG_OK;
+}
+
+// y = H_eff x (device pointers, FP64 I/O)
+dmrg_status Engine::heff(Bond& B, const double* x, double* y, int prec) {
+    DEV(dmrgdev::event_record(dev_, 0));
+    TRY(heff_launch(B, x, y, prec));
+    DEV(dmrgdev::event_record(dev_, 1));
+    heff_time_ += dmrgdev::event_elapsed(dev_, 0, 1);
+    return DMRG_OK;
+}
+
+dmrg_status Engine::heff_launch(Bond& B, const double* x, double* y, int prec) {
+    if (prec == dmrgdev::P_F64) {
+        for (size_t g = 0; g < B.groups.size(); ++g) {
+            void* bufs[5] = {B.Sops.pool.p, B.Eops.pool.p, (void*)x, z_.p, y};
+            TRY(run_gemm(prec, bufs, B.groups[g].p1));
+            TRY(run_gemm(prec, bufs, B.groups[g].p2));
+        }
+        return DMRG_OK;
+    }
+    TRY(ensure_lo(B, prec));
+    size_t es = prec == dmrgdev::P_F32 ? 4 : 2;
+    int64_t zmax = 0;
+    for (auto& g : B.groups) zmax = std::max(zmax, g.z_elems);
+    if (xlo_.bytes < (size_t)B.dim * es) TRY(alloc_buf(xlo_, std::max<int64_t>(B.dim, 1) * es));
+    if (ylo_.bytes < (size_t)B.dim * 4) TRY(alloc_buf(ylo_, std::max<int64_t>(B.dim, 1) * 4));
+    size_t zbytes = (size_t)std::max<int64_t>(zmax, 1) * es;
+    if (scr_a_.bytes < zbytes) TRY(alloc_buf(scr_a_, zbytes));
+    DEV(dmrgdev::convert(dev_, dmrgdev::P_F64, x, prec, xlo_.p, B.dim));
+    for (size_t g = 0; g < B.groups.size(); ++g) {
+        void* bufs[5] = {B.Sops.pool_lo.p, B.Eops.pool_lo.p, xlo_.p, scr_a_.p, ylo_.p};
+        TRY(run_gemm(prec, bufs, B.groups[g].p1, prec));          // Z in the operand precision
+        TRY(run_gemm(prec, bufs, B.groups[g].p2, dmrgdev::P_F32));
+    }
+    DEV(dmrgdev::convert(dev_, dmrgdev::P_F32, ylo_.p, dmrgdev::P_F64, y, B.dim));
+    return DMRG_OK;
+}
+
+// =============================================================== Davidson
+dmrg_status Engine::ensure_dv(int64_t n, int kmax) {
+    if (dv_cap_ >= n && dv_V_.p) return DMRG_OK;
+    int64_t cap = std::max<int64_t>(n, 1);
+    TRY(alloc_buf(dv_V_, (size_t)cap * kmax * sizeof(double)));
+    TRY(alloc_buf(dv_W_, (size_t)cap * kmax * sizeof(double)));
+    TRY(alloc_buf(dv_x_, cap * sizeof(double)));
+    TRY(alloc_buf(dv_hx_, cap * sizeof(double)));
+    TRY(alloc_buf(dv_r_, cap * sizeof(double)));
+    TRY(alloc_buf(dv_t_, cap * sizeof(double)));
+    TRY(alloc_buf(dv_small_, 4096 * sizeof(double)));
+    dv_cap_ = cap;
+    return DMRG_OK;
+}
+
+// Lowest eigenpair of H_eff from the guess in psi_: subspace V from the
+// normalised guess; correction r / (diag - theta) (|diag - theta| >= 1e-12);
+// classical Gram-Schmidt twice; restart to [x] at the maximum subspace;
+// converged when |H x - theta x| <= tol.  In the mixed modes expansion
+// products run in reduced precision and, once the residual of the
+// reduced-precision problem stalls (or passes the tolerance), the subspace is
+// restarted from [x, H64 x] with an FP64 product, so that the accepted residual
+// and the reported energy are FP64 quantities.
+dmrg_status Engine::davidson(Bond& B, double* theta_out, int64_t* nlo, int64_t* n64, bool* conv) {
+    const int64_t n = B.dim;
+    const int kmax = std::max(2, std::min(32, opt_.davidson_max_subspace));
+    TRY(ensure_dv(n, kmax));
+    double* Vm = dv_V_.d();
+    double* Wm = dv_W_.d();
+    double* G = dv_small_.d();          // kmax x kmax at ld 32
+    double* s = G + 32 * 32;            // 32
+    double* sc = s + 32;                // scalars: 0 theta, 1 |r|^2, 2 |t|^2, 3 |x|^2
+    double* cc = sc + 8;                // 32 (projection coefficients)
+    const int ldg = 32;
+    const int lowp = opt_.precision == DMRG_MIXED_FP32 ? dmrgdev::P_F32
+                     : opt_.precision == DMRG_MIXED_BF16 ? dmrgdev::P_BF16 : dmrgdev::P_F64;
+    bool in_low = lowp != dmrgdev::P_F64;
+    *nlo = 0;
+    *n64 = 0;
+    *conv = false;
+    // V0 = psi / |psi|
+    DEV(dmrgdev::dots(dev_, psi_.d(), 0, 1, psi_.d(), n, sc + 3));
+    DEV(dmrgdev::copy_scaled_inv_norm(dev_, psi_.d(), n, sc + 3, Vm));
+    TRY(heff(B, Vm, Wm, in_low ? lowp : dmrgdev::P_F64));
+    (in_low ? *nlo : *n64) += 1;
+    int k = 1;
+    DEV(dmrgdev::dots(dev_, Vm, n, 1, Wm, n, G));
+    double theta = 0.0, rn = 0.0, prev_rn = 1e300;
+    int stall = 0;
+    const double tol = opt_.davidson_tol;
+    while (true) {
+        DEV(dmrgdev::small_eigh(dev_, G, k, ldg, sc, s));
+        DEV(dmrgdev::combine(dev_, Vm, n, k, s, 1.0, n, dv_x_.d(), 0));
+        DEV(dmrgdev::combine(dev_, Wm, n, k, s, 1.0, n, dv_hx_.d(), 0));
+        DEV(dmrgdev::residual(dev_, dv_hx_.d(), dv_x_.d(), sc, n, dv_r_.d(), sc + 1));
+        double hs[2];
+        DEV(dmrgdev::d2h(dev_, hs, sc, 2 * sizeof(double)));
+        theta = hs[0];
+        rn = std::sqrt(std::max(hs[1], 0.0));
+        int64_t nprod = *nlo + *n64;
+        if (in_low) {
+            // leave reduced precision when its residual passes tol or stops improving
+            bool stalled = rn > 0.5 * prev_rn;
+            stall = stalled ? stall + 1 : 0;
+            if (rn <= tol || stall >= 2 || nprod >= opt_.davidson_max_iter) {
+                in_low = false;
+                // restart from x with an FP64 product
+                DEV(dmrgdev::dots(dev_, dv_x_.d(), 0, 1, dv_x_.d(), n, sc + 3));
+                DEV(dmrgdev::copy_scaled_inv_norm(dev_, dv_x_.d(), n, sc + 3, Vm));
+                TRY(heff(B, Vm, Wm, dmrgdev::P_F64));
+                *n64 += 1;
+                k = 1;
+                DEV(dmrgdev::dots(dev_, Vm, n, 1, Wm, n, G));
+                prev_rn = 1e300;
+                continue;
+            }
+            prev_rn = rn;
+        } else if (rn <= tol) {
+            *conv = true;
+            break;
+        }
+        if (nprod >= opt_.davidson_max_iter) break;
+        DEV(dmrgdev::precond(dev_, dv_r_.d(), B.diag.d(), sc, n, dv_t_.d()));
+        if (k >= kmax) {
+            DEV(dmrgdev::dots(dev_, dv_x_.d(), 0, 1, dv_x_.d(), n, sc + 3));
+            DEV(dmrgdev::copy_scaled_inv_norm(dev_, dv_x_.d(), n, sc + 3, Vm));
+            DEV(dmrgdev::copy_scaled_inv_norm(dev_, dv_hx_.d(), n, sc + 3, Wm));
+            k = 1;
+            DEV(dmrgdev::dots(dev_, Vm, n, 1, Wm, n, G));
+        }
+        DEV(dmrgdev::dots(dev_, dv_t_.d(), 0, 1, dv_t_.d(), n, sc + 2));
+        DEV(dmrgdev::scale_inv_norm(dev_, dv_t_.d(), n, sc + 2));
+        for (int pass = 0; pass < 2; ++pass) {
+            DEV(dmrgdev::dots(dev_, Vm, n, k, dv_t_.d(), n, cc));
+            DEV(dmrgdev::combine(dev_, Vm, n, k, cc, -1.0, n, dv_t_.d(), 1));
+        }
+        DEV(dmrgdev::dots(dev_, dv_t_.d(), 0, 1, dv_t_.d(), n, sc + 2));
+        double tn2;
+        DEV(dmrgdev::d2h(dev_, &tn2, sc + 2, sizeof(double)));
+        if (std::sqrt(std::max(tn2, 0.0)) < 1e-12) {
+            if (in_low) {
+                stall = 2;
+                prev_rn = 0.0;
+                continue;
+            }
+            break;
+        }
+        DEV(dmrgdev::copy_scaled_inv_norm(dev_, dv_t_.d(), n, sc + 2, Vm + (size_t)k * n));
+        TRY(heff(B, Vm + (size_t)k * n, Wm + (size_t)k * n, in_low ? lowp : dmrgdev::P_F64));
+        (in_low ? *nlo : *n64) += 1;
+        // new column and row of G = V^T W
+        DEV(dmrgdev::dots(dev_, Vm, n, k + 1, Wm + (size_t)k * n, n, G + k, ldg));
+        DEV(dmrgdev::dots(dev_, Wm, n, k, Vm + (size_t)k * n, n, G + (size_t)k * ldg));
+        ++k;
+    }
+    // psi <- x normalised
+    DEV(dmrgdev::dots(dev_, dv_x_.d(), 0, 1, dv_x_.d(), n, sc + 3));
+    DEV(dmrgdev::copy_scaled_inv_norm(dev_, dv_x_.d(), n, sc + 3, psi_.d()));
+    *theta_out = theta;
+    return DMRG_OK;
+}
+
+// ====================================================== random start
+dmrg_status Engine::random_psi(Bond& B, Buf& out) {
+    std::vector<double> h(B.dim);
+    for (size_t x = 0; x < B.pm_S.size(); ++x) {
+        const QN& q = B.S.mq[B.pm_S[x]];
+        int ds = B.S.md[B.pm_S[x]], de = B.E.md[B.pm_E[x]];
+        for (int a = 0; a < ds; ++a)
+            for (int b = 0; b < de; ++b)
+                h[B.poff[x] + (int64_t)a * de + b] =
+                    2.0 * u01(hkey({(int64_t)opt_.seed, 3, q.np, q.nn, q.tm, a, b})) - 1.0;
+    }
+    return upload(out, h);
+}
+
+// Selection isometry per sector: keep counts by integer largest remainder
+// (ties to the smaller sector), kept states = smallest SplitMix64 keys, in
+// index order; optionally multiplied by a hash-random Householder reflection.
+std::vector<std::vector<double>> Engine::selection_iso(const std::vector<int>& dims, int D, int tag, int pos,
+                                                       const std::vector<QN>& qs, bool mix,
+                                                       std::vector<int>& kept,
+                                                       std::vector<std::vector<int>>* chosen_out) {
+    int64_t total = 0;
+    for (int d : dims) total += d;
+    size_t ns = dims.size();
+    kept.assign(ns, 0);
+    if (total <= D) {
+        for (size_t x = 0; x < ns; ++x) kept[x] = dims[x];
+    } else {
+        std::vector<int64_t> rem(ns);
+        int64_t sum = 0;
+        for (size_t x = 0; x < ns; ++x) {
+            kept[x] = (int)(((int64_t)D * dims[x]) / total);
+            rem[x] = ((int64_t)D * dims[x]) % total;
+            sum += kept[x];
+        }
+        std::vector<size_t> ord(ns);
+        std::iota(ord.begin(), ord.end(), 0);
+        std::stable_sort(ord.begin(), ord.end(), [&](size_t a, size_t b) {
+            if (rem[a] != rem[b]) return rem[a] > rem[b];
+            return qs[a] < qs[b];
+        });
+        int64_t left = D - sum;
+        for (size_t y = 0; y < ns && left > 0; ++y) {
+            size_t x = ord[y];
+            if (kept[x] < dims[x]) {
+                kept[x]++;
+                left--;
+            }
+        }
+    }
+    std::vector<std::vector<double>> iso(ns);
+    if (chosen_out) chosen_out->assign(ns, {});
+    for (size_t x = 0; x < ns; ++x) {
+        int d = dims[x], k = kept[x];
+        if (k == 0) continue;
+        const QN& q = qs[x];
+        std::vector<std::pair<uint64_t, int>> keys(d);
+        for (int r = 0; r < d; ++r) keys[r] = {hkey({(int64_t)opt_.seed, tag, pos, q.np, q.nn, q.tm, r}), r};
+        std::sort(keys.begin(), keys.end());
+        std::vector<int> ch(k);
+        for (int c = 0; c < k; ++c) ch[c] = keys[c].second;
+        std::sort(ch.begin(), ch.end());
+        std::vector<double> U((size_t)d * k, 0.0);
+        for (int c = 0; c < k; ++c) U[(size_t)ch[c] * k + c] = 1.0;
+        if (mix && d > 1) {
+            std::vector<double> v(d);
+            double vv = 0.0;
+            for (int r = 0; r < d; ++r) {
+                v[r] = 2.0 * u01(hkey({(int64_t)opt_.seed, 4, pos, q.np, q.nn, q.tm, r})) - 1.0;
+                vv += v[r] * v[r];
+            }
+            double f = 2.0 / vv;
+            for (int r = 0; r < d; ++r)
+                for (int c = 0; c < k; ++c) U[(size_t)r * k + c] -= f * v[r] * v[ch[c]];
+        }
+        iso[x] = std::move(U);
+        if (chosen_out) (*chosen_out)[x] = ch;
+    }
+    return iso;
+}
+
+// ============================================================ initialise
+dmrg_status Engine::initialize(int D) {
+    cur_.reset();
+    psi_.reset();
+    L_.clear();
+    R_.clear();
+    L_.resize(N_ + 1);
+    R_.resize(N_ + 2);
+    L_[0] = vacuum('L', 0);
+    R_[N_] = vacuum('R', N_);
+    if (!L_[0] || !R_[N_]) return fail(DMRG_ERR_OUT_OF_MEMORY, "vacuum block");
+    for (int lo = N_ - 1; lo >= 2; --lo) {
+        const Stored& base = *R_[lo + 1];
+        std::set<QN> cand;
+        for (int sg = 0; sg < 2; ++sg)
+            for (const QN& q : base.basis.q) cand.insert(sg ? q + delta_[lo] : q);
+        std::vector<QN> allowed;
+        for (const QN& q : cand)
+            if (reachable(pre_[lo], T_ - q)) allowed.push_back(q);
+        auto blk = std::make_unique<Stored>();
+        blk->side = 'R';
+        blk->lo = lo;
+        blk->hi = N_;
+        OpSet eops;
+        TRY(enlarge(base, 'R', allowed, blk->comp, eops));
+        std::vector<int> kept;
+        std::vector<std::vector<int>> chosen;
+        auto iso = selection_iso(blk->comp.md, D, 1, lo, blk->comp.mq, !opt_.select_basis, kept, &chosen);
+        std::vector<int> keep_m, kdim;
+        std::vector<double> flat;
+        for (size_t m = 0; m < kept.size(); ++m) {
+            if (!kept[m]) continue;
+            keep_m.push_back((int)m);
+            kdim.push_back(kept[m]);
+            blk->basis.add(blk->comp.mq[m], kept[m]);
+            blk->comp_m.push_back((int)m);
+            blk->iso_off.push_back((int64_t)flat.size());
+            flat.insert(flat.end(), iso[m].begin(), iso[m].end());
+            size_t pad = (32 - flat.size() % 32) % 32;
+            flat.insert(flat.end(), pad, 0.0);
+        }
+        TRY(upload(blk->iso, flat));
+        bool normal_in = !normal_S(lo - 1);
+        TRY(renormalize(blk->comp, eops, normal_in, *blk, keep_m, kdim));
+        if (opt_.select_basis && base.has_cfg) {
+            blk->has_cfg = true;
+            for (size_t x = 0; x < keep_m.size(); ++x) {
+                int m = keep_m[x];
+                std::vector<uint64_t> comp;
+                for (int sg = 0; sg < 2; ++sg) {
+                    int si = blk->comp.msub[m][sg];
+                    if (si < 0) continue;
+                    for (uint64_t c : base.cfg[blk->comp.sub[si].base])
+                        comp.push_back(c | (sg ? (1ull << lo) : 0ull));
+                }
+                std::vector<uint64_t> v;
+                for (int r : chosen[m]) v.push_back(comp[r]);
+                blk->cfg.push_back(v);
+            }
+        }
+        R_[lo] = std::move(blk);
+    }
+    init_ = true;
+    dir_ = 0;
+    bond_ = 0;
+    fresh_ = false;
+    sweeps_done_ = 0;
+    TRY(setup_bond(0, cur_));
+    TRY(random_psi(*cur_, psi_));
+    return DMRG_OK;
+}
+
+// ===================================================== density matrix
+// rho of the S (left = true) or E sectors present in psi, with the
+// perturbation alpha * sum_O (O psi)(O psi)^T over c+ and c of the block's
+// sites.  rho blocks are dense (d x d) at roff[x] for psi block x.
+dmrg_status Engine::density_matrix(Bond& B, bool left, double alpha, Buf& rho, std::vector<int64_t>& roff,
+                                   std::vector<int>& rdim) {
+    const Enl &S = B.S, &E = B.E;
+    int nb = (int)B.pm_S.size();
+    roff.assign(nb, 0);
+    rdim.assign(nb, 0);
+    int64_t tot = 0;
+    for (int x = 0; x < nb; ++x) {
+        int d = left ? S.md[B.pm_S[x]] : E.md[B.pm_E[x]];
+        rdim[x] = d;
+        roff[x] = tot;
+        tot += ((int64_t)d * d + 31) / 32 * 32;
+    }
+    TRY(alloc_buf(rho, std::max<int64_t>(tot, 1) * sizeof(double)));
+    // bufs: 0 psi, 1 ops, 2 Phi, 3 rho
+    std::vector<std::vector<GemmChunk>> lists(nb);
+    GB g1;
+    int64_t phi = 0;
+    for (int x = 0; x < nb; ++x) {
+        int ds = S.md[B.pm_S[x]], de = E.md[B.pm_E[x]];
+        if (left) lists[x].push_back(GemmChunk{1.0, B.poff[x], B.poff[x], de, de, de, 0, 0, 0, 1});
+        else lists[x].push_back(GemmChunk{1.0, B.poff[x], B.poff[x], de, de, ds, 0, 0, 1, 0});
+    }
+    if (alpha != 0.0) {
+        const OpSet& ops = left ? B.Sops : B.Eops;
+        const Enl& en = left ? S : E;
+        int lo = left ? 0 : B.b + 1, hi = left ? B.b + 1 : N_;
+        for (int site = lo; site < hi; ++site) {
+            const Op* C = ops.get({'C', site, 0});
+            if (!C) continue;
+            for (int tr = 0; tr < 2; ++tr) {
+                // Phi = op(C) psi (left: rows; right: columns), per psi block
+                for (int x = 0; x < nb; ++x) {
+                    int mS = B.pm_S[x], mE = B.pm_E[x];
+                    int m_in = left ? mS : mE;
+                    int ds = S.md[mS], de = E.md[mE];
+                    // output merged sector of op(C) on m_in
+                    int m_out = -1;
+                    for (int i : en.msub[m_in]) {
+                        if (i < 0) continue;
+                        for (int q : C->acting(i, tr)) m_out = en.sub[tr ? C->blk[q].in : C->blk[q].out].m;
+                    }
+                    if (m_out < 0) continue;
+                    int x2 = left ? B.blk_of_S[m_out] : -1;
+                    if (!left) {
+                        int ms2 = S.find_m(T_ - E.mq[m_out]);
+                        x2 = ms2 >= 0 ? B.blk_of_S[ms2] : -1;
+                    }
+                    if (x2 < 0) continue;
+                    int dout = en.md[m_out];
+                    int rows = left ? dout : ds, cols = left ? de : dout;
+                    int64_t po = phi;
+                    phi += ((int64_t)rows * cols + 31) / 32 * 32;
+                    // every sub-row (left) / sub-column (right) of Phi: chunks over input subs
+                    for (int o : en.msub[m_out]) {
+                        if (o < 0) continue;
+                        g1.begin();
+                        for (int i : en.msub[m_in]) {
+                            if (i < 0) continue;
+                            for (int q : C->acting(i, tr)) {
+                            const Blk* b = &C->blk[q];
+                            if ((tr ? b->in : b->out) != o) continue;
+                            if (left)
+                                g1.chunk(1.0, 1, b->off, b->cols, tr, 0, B.poff[x] + (int64_t)en.sub[i].off * de, de,
+                                         false, en.sub[i].dim);
+                            else
+                                g1.chunk(1.0, 0, B.poff[x] + en.sub[i].off, de, false, 1, b->off, b->cols, !tr,
+                                         en.sub[i].dim);
+                            }
+                        }
+                        if (left) g1.end(2, po + (int64_t)en.sub[o].off * cols, cols, en.sub[o].dim, cols, 0);
+                        else g1.end(2, po + en.sub[o].off, cols, rows, en.sub[o].dim, 0);
+                    }
+                    if (left) lists[x2].push_back(GemmChunk{alpha, po, po, cols, cols, cols, 2, 2, 0, 1});
+                    else lists[x2].push_back(GemmChunk{alpha, po, po, cols, cols, rows, 2, 2, 1, 0});
+                }
+            }
+        }
+    }
+    GB g2;
+    for (int x = 0; x < nb; ++x) {
+        g2.begin();
+        for (auto& c : lists[x]) g2.chunks.push_back(c);
+        g2.end(3, roff[x], rdim[x], rdim[x], rdim[x], 0);
+    }
+    Buf phib;
+    TRY(alloc_buf(phib, std::max<int64_t>(phi, 1) * sizeof(double)));
+    GemmPlan p1, p2;
+    TRY(finish_plan(*this, g1, p1));
+    TRY(finish_plan(*this, g2, p2));
+    const OpSet& ops = left ? B.Sops : B.Eops;
+    void* bufs[4] = {psi_.p, ops.pool.p, phib.p, rho.p};
+    TRY(run_gemm(dmrgdev::P_F64, bufs, p1));
+    TRY(run_gemm(dmrgdev::P_F64, bufs, p2));
+    DEV(dmrgdev::sync(dev_));
+    return DMRG_OK;
+}
+
+// ================================================ truncate + next bond
+dmrg_status Engine::truncate_and_move(int D, double alpha, double* disc) {
+    Bond& B = *cur_;
+    const bool left = dir_ == 0;
+    const int b = B.b;
+    const Enl& en = left ? B.S : B.E;
+    int nb = (int)B.pm_S.size();
+    // merged sectors of en present in psi, in en order
+    std::vector<int> pm(nb);
+    for (int x = 0; x < nb; ++x) pm[x] = left ? B.pm_S[x] : B.pm_E[x];
+    std::vector<int> mpos(en.mq.size(), -1);   // merged -> psi block
+    for (int x = 0; x < nb; ++x) mpos[pm[x]] = x;
+    std::vector<int> keep_m, kdim;
+    std::vector<double> flat;
+    std::vector<int64_t> iso_off;
+    std::vector<std::vector<int>> chosen;
+    *disc = 0.0;
+    auto blk = std::make_unique<Stored>();
+    blk->side = left ? 'L' : 'R';
+    blk->lo = left ? 0 : b + 1;
+    blk->hi = left ? b + 1 : N_;
+    if (opt_.select_basis) {
+        std::vector<int> dims;
+        std::vector<QN> qs;
+        std::vector<int> ms;
+        for (size_t m = 0; m < en.mq.size(); ++m)
+            if (mpos[m] >= 0) {
+                dims.push_back(en.md[m]);
+                qs.push_back(en.mq[m]);
+                ms.push_back((int)m);
+            }
+        std::vector<int> kept;
+        auto iso = selection_iso(dims, D, left ? 2 : 1, b + 1, qs, false, kept, &chosen);
+        std::vector<std::vector<int>> ch2;
+        for (size_t y = 0; y < ms.size(); ++y) {
+            if (!kept[y]) continue;
+            keep_m.push_back(ms[y]);
+            kdim.push_back(kept[y]);
+            iso_off.push_back((int64_t)flat.size());
+            flat.insert(flat.end(), iso[y].begin(), iso[y].end());
+            flat.insert(flat.end(), (32 - flat.size() % 32) % 32, 0.0);
+            ch2.push_back(chosen[y]);
+        }
+        chosen = ch2;
+        TRY(upload(blk->iso, flat));
+    } else {
+        Buf rho;
+        std::vector<int64_t> roff;
+        std::vector<int> rdim;
+        TRY(density_matrix(B, left, alpha, rho, roff, rdim));
+        Buf w;
+        int64_t wtot = 0;
+        std::vector<int64_t> woff(nb);
+        for (int x = 0; x < nb; ++x) {
+            woff[x] = wtot;
+            wtot += rdim[x];
+        }
+        TRY(alloc_buf(w, std::max<int64_t>(wtot, 1) * sizeof(double)));
+        for (int x = 0; x < nb; ++x) DEV(dmrgdev::syevd(dev_, rdim[x], rho.d() + roff[x], w.d() + woff[x]));
+        std::vector<double> hw(wtot);
+        DEV(dmrgdev::d2h(dev_, hw.data(), w.p, wtot * sizeof(double)));
+        double tr = 0.0;
+        for (double v : hw) tr += v;
+        struct Wt {
+            double w;
+            int x, e;
+        };
+        std::vector<Wt> all;
+        // in merged-sector order, eigenvalues ascending within a sector (stable sort below
+        // orders equal weights by sector then index, as the reference listing does)
+        for (int x = 0; x < nb; ++x)
+            for (int e = 0; e < rdim[x]; ++e) all.push_back({hw[woff[x] + e] / tr, x, e});
+        std::stable_sort(all.begin(), all.end(), [](const Wt& a, const Wt& c) { return a.w > c.w; });
+        int64_t cnt = (int64_t)all.size();
+        int64_t nk = std::min<int64_t>(D, cnt), n0 = nk;
+        while (nk > 0 && nk < cnt && all[nk - 1].w - all[nk].w <= opt_.tie_tol) --nk;
+        if (nk == 0) {
+            nk = n0;
+            while (nk < cnt && all[nk - 1].w - all[nk].w <= opt_.tie_tol) ++nk;
+        }
+        double kept_w = 0.0;
+        std::vector<std::vector<int>> sel(nb);
+        for (int64_t y = 0; y < nk; ++y) {
+            kept_w += all[y].w;
+            sel[all[y].x].push_back(all[y].e);
+        }
+        *disc = std::max(0.0, 1.0 - kept_w);
+        // U per kept sector: eigenvectors in descending weight order
+        Buf idxb;
+        std::vector<int32_t> idx;
+        std::vector<std::array<int64_t, 3>> jobs;   // x, idx offset, k
+        int64_t utot = 0;
+        for (size_t m = 0; m < en.mq.size(); ++m) {
+            int x = mpos[m];
+            if (x < 0 || sel[x].empty()) continue;
+            auto& s = sel[x];
+            std::sort(s.begin(), s.end(), [&](int a, int c) { return hw[woff[x] + a] > hw[woff[x] + c]; });
+            keep_m.push_back((int)m);
+            kdim.push_back((int)s.size());
+            iso_off.push_back(utot);
+            jobs.push_back({x, (int64_t)idx.size(), (int64_t)s.size()});
+            idx.insert(idx.end(), s.begin(), s.end());
+            utot += ((int64_t)rdim[x] * s.size() + 31) / 32 * 32;
+        }
+        TRY(upload(idxb, idx));
+        TRY(alloc_buf(blk->iso, std::max<int64_t>(utot, 1) * sizeof(double)));
+        for (size_t y = 0; y < jobs.size(); ++y) {
+            int x = (int)jobs[y][0];
+            DEV(dmrgdev::gather_evecs(dev_, rho.d() + roff[x], rdim[x], idxb.as<int32_t>() + jobs[y][1],
+                                      (int)jobs[y][2], blk->iso.d() + iso_off[y]));
+        }
+        DEV(dmrgdev::sync(dev_));
+    }
+    for (size_t y = 0; y < keep_m.size(); ++y) {
+        blk->basis.add(en.mq[keep_m[y]], kdim[y]);
+        blk->comp_m.push_back(keep_m[y]);
+    }
+    blk->iso_off = iso_off;
+    blk->comp = en;
+    bool normal_in = left ? normal_S(b) : !normal_S(b);
+    TRY(renormalize(en, left ? B.Sops : B.Eops, normal_in, *blk, keep_m, kdim));
+    const Stored& base = left ? *L_[b] : *R_[b + 2];
+    if (opt_.select_basis && base.has_cfg) {
+        blk->has_cfg = true;
+        for (size_t y = 0; y < keep_m.size(); ++y) {
+            int m = keep_m[y];
+            std::vector<uint64_t> comp;
+            for (int sg = 0; sg < 2; ++sg) {
+                int si = en.msub[m][sg];
+                if (si < 0) continue;
+                for (uint64_t c : base.cfg[en.sub[si].base]) comp.push_back(c | (sg ? (1ull << en.site) : 0ull));
+            }
+            std::vector<uint64_t> v;
+            for (int r : chosen[y]) v.push_back(comp[r]);
+            blk->cfg.push_back(v);
+        }
+    }
+    // next bond and prediction
+    int nbond = left ? b + 1 : b - 1;
+    std::unique_ptr<Bond> NB;
+    if (left) L_[b + 1] = std::move(blk);
+    else R_[b + 1] = std::move(blk);
+    TRY(setup_bond(nbond, NB));
+    Bond& B2 = *NB;
+    const Stored& nw = left ? *L_[b + 1] : *R_[b + 1];
+    // Phi: left: U_m^T psi_m (k x dE) ; right: psi_m V (dS x k)
+    GB g1, g2;
+    std::vector<int64_t> phoff(nb, -1);
+    int64_t ph = 0;
+    std::vector<int> newx(en.mq.size(), -1);
+    for (size_t y = 0; y < keep_m.size(); ++y) newx[keep_m[y]] = (int)y;
+    for (int x = 0; x < nb; ++x) {
+        int m = pm[x];
+        int y = newx[m];
+        if (y < 0) continue;
+        int ds = B.S.md[B.pm_S[x]], de = B.E.md[B.pm_E[x]], k = kdim[y];
+        phoff[x] = ph;
+        if (left) {
+            ph += ((int64_t)k * de + 31) / 32 * 32;
+            g1.begin();
+            g1.chunk(1.0, 1, nw.iso_off[y], k, true, 0, B.poff[x], de, false, ds);
+            g1.end(2, phoff[x], de, k, de, 0);
+        } else {
+            ph += ((int64_t)ds * k + 31) / 32 * 32;
+            g1.begin();
+            g1.chunk(1.0, 0, B.poff[x], de, false, 1, nw.iso_off[y], k, false, de);
+            g1.end(2, phoff[x], k, ds, k, 0);
+        }
+    }
+    // bufs: 0 psi(old), 1 new iso, 2 Phi, 3 psi(new), 4 far iso (R_{b+2} for L->R, L_b for R->L)
+    const Stored& far = left ? *R_[b + 2] : *L_[b];
+    int nb2 = (int)B2.pm_S.size();
+    std::vector<std::vector<GemmChunk>> lists(nb2 * 4);
+    auto sid = [&](int x2, int i, int j) { return x2 * 4 + B2.S.sub[i].sigma * 2 + B2.E.sub[j].sigma; };
+    for (int x = 0; x < nb; ++x) {
+        if (phoff[x] < 0) continue;
+        int y = newx[pm[x]];
+        int k = kdim[y];
+        if (left) {
+            // columns of Phi: E sub-sectors j = (sigma_{b+1}, R_{b+2} sector r)
+            int de = B.E.md[B.pm_E[x]];
+            for (int j : B.E.msub[B.pm_E[x]]) {
+                if (j < 0) continue;
+                const Sub& sj = B.E.sub[j];
+                int i2 = B2.S.find_sub(y, sj.sigma);
+                if (i2 < 0) continue;
+                int x2 = B2.blk_of_S[B2.S.sub[i2].m];
+                if (x2 < 0) continue;
+                int r = sj.base;   // sector of R_{b+2}
+                int kr = far.basis.d[r];
+                int cm = far.comp_m[r];
+                for (int c : far.comp.msub[cm]) {
+                    if (c < 0) continue;
+                    const Sub& sc = far.comp.sub[c];
+                    int j2 = B2.E.find_sub(sc.base, sc.sigma);
+                    if (j2 < 0 || B2.E.sub[j2].m != B2.pm_E[x2]) continue;
+                    lists[sid(x2, i2, j2)].push_back(GemmChunk{1.0, phoff[x] + sj.off, far.iso_off[r] + (int64_t)sc.off * kr,
+                                                               de, kr, kr, 2, 4, 0, 1});
+                }
+            }
+        } else {
+            // rows of Phi: S sub-sectors i = (L_b sector l, sigma_b)
+            for (int i : B.S.msub[B.pm_S[x]]) {
+                if (i < 0) continue;
+                const Sub& si = B.S.sub[i];
+                int j2 = B2.E.find_sub(y, si.sigma);
+                if (j2 < 0) continue;
+                int ms2 = B2.S.find_m(T_ - B2.E.sub[j2].q);
+                if (ms2 < 0) continue;
+                int x2 = B2.blk_of_S[ms2];
+                if (x2 < 0) continue;
+                int l = si.base;
+                int kl = far.basis.d[l];
+                int cm = far.comp_m[l];
+                for (int c : far.comp.msub[cm]) {
+                    if (c < 0) continue;
+                    const Sub& sc = far.comp.sub[c];
+                    int i2 = B2.S.find_sub(sc.base, sc.sigma);
+                    if (i2 < 0 || B2.S.sub[i2].m != B2.pm_S[x2]) continue;
+                    lists[sid(x2, i2, j2)].push_back(GemmChunk{1.0, far.iso_off[l] + (int64_t)sc.off * kl,
+                                                               phoff[x] + (int64_t)si.off * k, kl, k, kl, 4, 2, 0, 0});
+                }
+            }
+        }
+    }
+    for (int x2 = 0; x2 < nb2; ++x2)
+        for (int i : B2.S.msub[B2.pm_S[x2]])
+            for (int j : B2.E.msub[B2.pm_E[x2]]) {
+                if (i < 0 || j < 0) continue;
+                g2.begin();
+                for (auto& c : lists[sid(x2, i, j)]) g2.chunks.push_back(c);
+                int ldy = B2.E.md[B2.pm_E[x2]];
+                g2.end(3, B2.poff[x2] + (int64_t)B2.S.sub[i].off * ldy + B2.E.sub[j].off, ldy, B2.S.sub[i].dim,
+                       B2.E.sub[j].dim, 0);
+            }
+    Buf phib, npsi;
+    TRY(alloc_buf(phib, std::max<int64_t>(ph, 1) * sizeof(double)));
+    TRY(alloc_buf(npsi, std::max<int64_t>(B2.dim, 1) * sizeof(double)));
+    GemmPlan p1, p2;
+    TRY(finish_plan(*this, g1, p1));
+    TRY(finish_plan(*this, g2, p2));
+    void* bufs[5] = {psi_.p, nw.iso.p, phib.p, npsi.p, far.iso.p};
+    TRY(run_gemm(dmrgdev::P_F64, bufs, p1));
+    TRY(run_gemm(dmrgdev::P_F64, bufs, p2));
+    // fall back to the hash-random start if the guess vanished
+    if (!scal_.p) TRY(alloc_buf(scal_, 64 * sizeof(double)));
+    DEV(dmrgdev::dots(dev_, npsi.d(), 0, 1, npsi.d(), B2.dim, scal_.d()));
+    double nn = 0.0;
+    DEV(dmrgdev::d2h(dev_, &nn, scal_.p, sizeof(double)));
+    psi_ = std::move(npsi);
+    if (!(std::sqrt(std::max(nn, 0.0)) >= 1e-10)) TRY(random_psi(B2, psi_));
+    cur_ = std::move(NB);
+    return DMRG_OK;
+}
+
+// =============================================================== sweeps
+dmrg_status Engine::steps(const int32_t* ordering, int D, int64_t max_steps, bool until_sweep_end,
+                          dmrg_sweep_stats* st) {
+    if (!loaded_) return fail(DMRG_ERR_STATE, "no Hamiltonian loaded");
+    if (D < 1) return fail(DMRG_ERR_ARG, "D must be >= 1");
+    if (N_ < 2) return fail(DMRG_ERR_ARG, "need at least 2 sites for a two-site sweep");
+    std::vector<int> before = order_;
+    TRY(set_order(ordering));
+    double t0 = now();
+    if (!init_) {
+        TRY(initialize(D));
+        sweep_min_ = INFINITY;
+        sweep_steps_ = 0;
+        acc_ = dmrg_sweep_stats{};
+    }
+    if (sweep_steps_ == 0) {
+        acc_ = dmrg_sweep_stats{};
+        sweep_min_ = INFINITY;
+    }
+    TRY(ensure_dv(cur_->dim, std::max(2, std::min(32, opt_.davidson_max_subspace))));
+    dmrg_status ret = DMRG_OK;
+    int64_t done = 0;
+    while (done < max_steps) {
+        // solve at the current bond unless psi is its converged eigenvector
+        if (!fresh_) {
+            double th;
+            int64_t nlo, n64;
+            bool conv;
+            heff_time_ = 0.0;
+            TRY(davidson(*cur_, &th, &nlo, &n64, &conv));
+            acc_.heff_seconds += heff_time_;
+            acc_.heff_flops += cur_->flops * (double)(nlo + n64);
+            acc_.products_low += nlo;
+            acc_.products_fp64 += n64;
+            acc_.solves += 1;
+            if (!conv) {
+                acc_.not_converged += 1;
+                ret = DMRG_WARN_NOT_CONVERGED;
+            }
+            theta_ = th;
+            fresh_ = true;
+        }
+        sweep_min_ = std::min(sweep_min_, theta_);
+        ++done;
+        ++sweep_steps_;
+        acc_.steps += 1;
+        bool last = dir_ == 0 ? bond_ == N_ - 2 : bond_ == 0;
+        if (last) {
+            if (dir_ == 0) {
+                dir_ = 1;   // turn: same bond, same state
+            } else {
+                dir_ = 0;
+                sweeps_done_ += 1;
+                have_energy_ = true;
+                energy_ = sweep_min_;
+                acc_.energy = sweep_min_;
+                acc_.last_theta = theta_;
+                acc_.sweep_seconds = now() - t0;
+                if (st) *st = acc_;
+                sweep_steps_ = 0;
+                if (until_sweep_end) return ret;
+                acc_ = dmrg_sweep_stats{};
+                sweep_min_ = INFINITY;
+                t0 = now();
+            }
+            continue;
+        }
+        double alpha = sweeps_done_ < opt_.noise_sweeps ? opt_.noise : 0.0;
+        double disc = 0.0;
+        double tr0 = now();
+        TRY(truncate_and_move(D, alpha, &disc));
+        acc_.renorm_seconds += now() - tr0;
+        acc_.discarded_max = std::max(acc_.discarded_max, disc);
+        acc_.discarded_sum += disc;
+        bond_ = cur_->b;
+        fresh_ = false;
+        TRY(ensure_dv(cur_->dim, std::max(2, std::min(32, opt_.davidson_max_subspace))));
+    }
+    acc_.energy = sweep_min_;
+    acc_.last_theta = theta_;
+    acc_.sweep_seconds += now() - t0;
+    if (st) *st = acc_;
+    return ret;
+}
+
+// ========================================================== queries
+dmrg_status Engine::layout(int32_t* bond, int64_t* dim, int32_t* nsec, int32_t* qn, int64_t* dims) {
+    if (!cur_) return fail(DMRG_ERR_STATE, "no current bond (run a sweep first)");
+    const Bond& B = *cur_;
+    if (bond) *bond = B.b;
+    if (dim) *dim = B.dim;
+    if (nsec) *nsec = (int32_t)B.pm_S.size();
+    for (size_t x = 0; x < B.pm_S.size(); ++x) {
+        const QN& q = B.S.mq[B.pm_S[x]];
+        if (qn) {
+            qn[3 * x] = q.np;
+            qn[3 * x + 1] = q.nn;
+            qn[3 * x + 2] = q.tm;
+        }
+        if (dims) {
+            dims[2 * x] = B.S.md[B.pm_S[x]];
+            dims[2 * x + 1] = B.E.md[B.pm_E[x]];
+        }
+    }
+    return DMRG_OK;
+}
+
+dmrg_status Engine::apply(const double* x, double* y, int prec) {
+    if (!cur_) return fail(DMRG_ERR_STATE, "no current bond (run a sweep first)");
+    if (!x || !y) return fail(DMRG_ERR_ARG, "null vector");
+    if (prec < 0 || prec > 2) return fail(DMRG_ERR_ARG, "precision must be 0, 1 or 2");
+    return heff_launch(*cur_, x, y, prec);
+}
+
+dmrg_status Engine::energy(double* E) {
+    if (!E) return fail(DMRG_ERR_ARG, "null output");
+    if (!have_energy_) return fail(DMRG_ERR_STATE, "no completed sweep");
+    *E = energy_;
+    return DMRG_OK;
+}
+
+dmrg_status Engine::get_psi(double* host) {
+    if (!cur_ || !psi_.p) return fail(DMRG_ERR_STATE, "no state");
+    if (!host) return fail(DMRG_ERR_ARG, "null output");
+    DEV(dmrgdev::sync(dev_));
+    DEV(dmrgdev::d2h(dev_, host, psi_.p, cur_->dim * sizeof(double)));
+    return DMRG_OK;
+}
+
+dmrg_status Engine::configs(uint64_t* out) {
+    if (!cur_) return fail(DMRG_ERR_STATE, "no current bond");
+    const Bond& B = *cur_;
+    const Stored& L = *L_[B.b];
+    const Stored& R = *R_[B.b + 2];
+    if (!L.has_cfg || !R.has_cfg) return fail(DMRG_ERR_STATE, "block bases are not determinant selections");
+    for (size_t x = 0; x < B.pm_S.size(); ++x) {
+        std::vector<uint64_t> sc, ec;
+        for (int i : B.S.msub[B.pm_S[x]]) {
+            if (i < 0) continue;
+            for (uint64_t c : L.cfg[B.S.sub[i].base]) sc.push_back(c | (B.S.sub[i].sigma ? (1ull << B.S.site) : 0ull));
+        }
+        for (int j : B.E.msub[B.pm_E[x]]) {
+            if (j < 0) continue;
+            for (uint64_t c : R.cfg[B.E.sub[j].base]) ec.push_back(c | (B.E.sub[j].sigma ? (1ull << B.E.site) : 0ull));
+        }
+        int64_t o = B.poff[x];
+        for (uint64_t a : sc)
+            for (uint64_t c : ec) out[o++] = a | c;
+    }
+    return DMRG_OK;
+}
+
+}  // namespace dm

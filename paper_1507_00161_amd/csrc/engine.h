@@ -1,0 +1,348 @@
+// engine.h - host side of the two-site DMRG: quantum-number bookkeeping,
+// block-operator catalogue and blocking recipes, work lists for the device
+// kernels, and the sweep / Davidson / truncation control.
+#pragma once
+#include <array>
+#include <cstdint>
+#include <map>
+#include <memory>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/dmrg.h"
+#include "device.h"
+
+namespace dm {
+
+struct QN {
+    int np = 0, nn = 0, tm = 0;
+    QN() = default;
+    QN(int a, int b, int c) : np(a), nn(b), tm(c) {}
+    bool operator<(const QN& o) const {
+        if (np != o.np) return np < o.np;
+        if (nn != o.nn) return nn < o.nn;
+        return tm < o.tm;
+    }
+    bool operator==(const QN& o) const { return np == o.np && nn == o.nn && tm == o.tm; }
+    bool operator!=(const QN& o) const { return !(*this == o); }
+    QN operator+(const QN& o) const { return {np + o.np, nn + o.nn, tm + o.tm}; }
+    QN operator-(const QN& o) const { return {np - o.np, nn - o.nn, tm - o.tm}; }
+    QN operator-() const { return {-np, -nn, -tm}; }
+    int n() const { return np + nn; }
+};
+
+// operator catalogue key: H; C i (c+_i); R i; A i j; B i j; P i j; Q i j
+struct Key {
+    char k;
+    int i, j;
+    bool operator<(const Key& o) const {
+        if (k != o.k) return k < o.k;
+        if (i != o.i) return i < o.i;
+        return j < o.j;
+    }
+};
+
+class Engine;
+
+// owning device allocation, counted against the context's memory cap
+struct Buf {
+    Engine* eng = nullptr;
+    void* p = nullptr;
+    size_t bytes = 0;
+    Buf() = default;
+    Buf(const Buf&) = delete;
+    Buf& operator=(const Buf&) = delete;
+    Buf(Buf&& o) noexcept { *this = std::move(o); }
+    Buf& operator=(Buf&& o) noexcept;
+    ~Buf() { reset(); }
+    void reset();
+    double* d() const { return static_cast<double*>(p); }
+    template <class T> T* as() const { return static_cast<T*>(p); }
+};
+
+struct Basis {
+    std::vector<QN> q;
+    std::vector<int> d;
+    std::map<QN, int> idx;
+    int find(const QN& x) const {
+        auto it = idx.find(x);
+        return it == idx.end() ? -1 : it->second;
+    }
+    void add(const QN& x, int dim) {
+        idx[x] = (int)q.size();
+        q.push_back(x);
+        d.push_back(dim);
+    }
+    int64_t total() const {
+        int64_t t = 0;
+        for (int x : d) t += x;
+        return t;
+    }
+};
+
+// Enlarged block S = L*s or E = s*R.  Its states are grouped in sub-sectors
+// (base sector, site occupation sigma); sub-sectors with equal quantum
+// numbers form a merged sector whose rows list sigma = 0 first.
+struct Sub {
+    int m, base, sigma, off, dim;
+    QN q;
+};
+struct Enl {
+    char side = 'L';
+    int site = 0;
+    QN dsite;
+    std::vector<QN> mq;
+    std::vector<int> md;
+    std::vector<Sub> sub;
+    std::vector<std::array<int, 2>> msub;       // merged -> sub index per sigma (-1: absent)
+    std::map<std::pair<int, int>, int> sub_of;  // (base sector, sigma) -> sub index
+    std::map<QN, int> midx;
+    int find_m(const QN& x) const {
+        auto it = midx.find(x);
+        return it == midx.end() ? -1 : it->second;
+    }
+    int find_sub(int base, int sigma) const {
+        auto it = sub_of.find({base, sigma});
+        return it == sub_of.end() ? -1 : it->second;
+    }
+};
+
+struct Blk {
+    int out, in;
+    int64_t off;
+    int rows, cols;
+};
+// Block-sparse operator with one quantum-number shift dq.  On a stored block
+// (merged sectors) an input sector has at most one block; on an enlarged block
+// (sub-sectors) it can have two, whose site occupations differ.
+struct Op {
+    QN dq;
+    int par = 0;
+    std::vector<Blk> blk;
+    std::unordered_map<int, std::vector<int>> by_in, by_out;
+    const std::vector<int>& ins(int s) const {
+        static const std::vector<int> none;
+        auto it = by_in.find(s);
+        return it == by_in.end() ? none : it->second;
+    }
+    const std::vector<int>& outs(int s) const {
+        static const std::vector<int> none;
+        auto it = by_out.find(s);
+        return it == by_out.end() ? none : it->second;
+    }
+    // the single block on an input (output) sector of a stored block
+    const Blk* in_blk(int s) const {
+        auto& v = ins(s);
+        return v.empty() ? nullptr : &blk[v[0]];
+    }
+    const Blk* out_blk(int s) const {
+        auto& v = outs(s);
+        return v.empty() ? nullptr : &blk[v[0]];
+    }
+    // blocks acting on sector s of op (trans = 0) or of op^T (trans = 1)
+    const std::vector<int>& acting(int s, bool trans) const { return trans ? outs(s) : ins(s); }
+    void index() {
+        by_in.clear();
+        by_out.clear();
+        for (size_t x = 0; x < blk.size(); ++x) {
+            by_in[blk[x].in].push_back((int)x);
+            by_out[blk[x].out].push_back((int)x);
+        }
+    }
+};
+
+struct OpSet {
+    std::map<Key, int> idx;
+    std::vector<Op> ops;
+    std::vector<Key> keys;
+    Buf pool;               // FP64 blocks
+    Buf pool_lo;            // reduced-precision copy (mixed modes)
+    int lo_prec = -1;
+    int64_t size = 0;       // elements
+    const Op* get(const Key& k) const {
+        auto it = idx.find(k);
+        return it == idx.end() ? nullptr : &ops[it->second];
+    }
+    int find(const Key& k) const {
+        auto it = idx.find(k);
+        return it == idx.end() ? -1 : it->second;
+    }
+    int add(const Key& k, Op&& op) {
+        int x = (int)ops.size();
+        idx[k] = x;
+        keys.push_back(k);
+        ops.push_back(std::move(op));
+        return x;
+    }
+    int64_t alloc_block(int rows, int cols) {
+        int64_t off = size;
+        size += ((int64_t)rows * cols + 31) / 32 * 32;
+        return off;
+    }
+};
+
+// stored (renormalised) left block L = sites [0, hi) or right block R = sites [lo, N)
+struct Stored {
+    char side = 'L';
+    int lo = 0, hi = 0;
+    bool normal = true;            // normal (A, B) rather than complementary (P, Q) pair ops
+    Basis basis;
+    OpSet ops;
+    // isometry that created the block from its composite (for prediction):
+    // kept sector x <- composite merged sector comp_m[x], comp_dim x kept, row-major
+    Enl comp;
+    std::vector<int> comp_m;
+    std::vector<int64_t> iso_off;
+    Buf iso;
+    bool has_cfg = false;
+    std::vector<std::vector<uint64_t>> cfg;   // determinant per state (chain-position bits)
+    int length() const { return hi - lo; }
+};
+
+// one term of H_eff: y += coef * sign * op(A) psi op(B)^T, sign = (-1)^{par n(S sector)}
+// taken on the input S sector (sign_out = 0) or the output one (sign_out = 1)
+struct Term {
+    double coef;
+    int a, b;          // op index in S / E op sets, -1 = identity
+    bool ta, tb;
+    bool sign_out;
+    int par;
+};
+
+struct GemmPlan {
+    Buf tasks, chunks;
+    int ntasks = 0;
+    int64_t nchunks = 0;
+    double flops = 0.0;
+};
+
+struct HeffGroup {
+    GemmPlan p1, p2;    // Z = psi op(B)^T ; y (+)= op(A) Z
+    int64_t z_elems = 0;
+};
+
+struct Bond {
+    int b = 0;
+    Enl S, E;
+    OpSet Sops, Eops;
+    // psi layout: merged S sector pm_S[x] with E sector pm_E[x], offset poff[x]
+    std::vector<int> pm_S, pm_E;
+    std::vector<int64_t> poff;
+    std::vector<int> blk_of_S;     // S merged -> psi block (-1)
+    int64_t dim = 0;
+    std::vector<Term> terms;
+    std::vector<HeffGroup> groups;
+    double flops = 0.0;
+    Buf diag;
+    int lo_prec = -1;
+};
+
+class Engine {
+public:
+    Engine(dmrgdev::Ctx* dev, const dmrg_options& opt) : dev_(dev), opt_(opt) {}
+    ~Engine();
+
+    dmrg_status load(int n, const int32_t* species, const int32_t* two_m, const double* eps,
+                     const double* V, int n_p, int n_n, int two_M);
+    dmrg_status steps(const int32_t* ordering, int D, int64_t max_steps, bool until_sweep_end,
+                      dmrg_sweep_stats* st);
+    dmrg_status layout(int32_t* bond, int64_t* dim, int32_t* nsec, int32_t* qn, int64_t* dims);
+    dmrg_status apply(const double* x, double* y, int prec);
+    dmrg_status energy(double* E);
+    dmrg_status get_psi(double* host);
+    dmrg_status configs(uint64_t* out);
+
+    const std::string& error() const { return err_; }
+    dmrg_status fail(dmrg_status s, const std::string& msg) {
+        err_ = msg;
+        return s;
+    }
+    void* dalloc(size_t bytes);
+    void dfree(void* p, size_t bytes);
+    dmrgdev::Ctx* dev() const { return dev_; }
+
+    // used by the plan builders
+    double V(int i, int j, int k, int l) const {
+        return V_[(((size_t)i * N_ + j) * N_ + k) * N_ + l];
+    }
+    int N() const { return N_; }
+    const QN& delta(int i) const { return delta_[i]; }
+    double eps(int i) const { return eps_[i]; }
+    bool normal_S(int b) const { return b + 1 <= N_ - b - 1; }
+    bool left_normal(int len) const { return normal_S(len); }
+    bool right_normal(int lo) const { return N_ - lo + 1 < lo - 1; }
+    template <class T> dmrg_status upload(Buf& b, const std::vector<T>& v);
+    dmrg_status alloc_buf(Buf& b, size_t bytes);
+
+private:
+    dmrgdev::Ctx* dev_;
+    dmrg_options opt_;
+    std::string err_;
+    int N_ = 0;
+    std::vector<int> sp0_, tm0_;
+    std::vector<double> eps0_, V0_;
+    std::vector<int> order_;
+    std::vector<double> eps_, V_;
+    std::vector<QN> delta_;
+    QN T_;
+    bool loaded_ = false;
+    // per-species subset sums of 2m: ok[k][tm + off] for k particles
+    struct Reach {
+        int off = 0, width = 0;
+        std::vector<std::vector<char>> p, n;
+    };
+    std::vector<Reach> pre_;     // pre_[b]: sites 0..b-1
+    size_t mem_used_ = 0;
+
+    // DMRG state
+    bool init_ = false;
+    int sweeps_done_ = 0;
+    int dir_ = 0, bond_ = 0;     // position in the sweep schedule
+    bool fresh_ = false;
+    std::vector<std::unique_ptr<Stored>> L_, R_;
+    std::unique_ptr<Bond> cur_;
+    Buf psi_;
+    double theta_ = 0.0;
+    bool have_energy_ = false;
+    double energy_ = 0.0;
+    double sweep_min_ = 0.0;
+    int sweep_steps_ = 0;
+    dmrg_sweep_stats acc_{};
+    // Davidson workspace
+    Buf dv_V_, dv_W_, dv_x_, dv_hx_, dv_r_, dv_t_, dv_small_;
+    int64_t dv_cap_ = 0;
+    // scratch
+    Buf z_, xlo_, ylo_, scr_a_, scr_b_, scal_;
+    double heff_time_ = 0.0;   // device seconds of H_eff products in the current solve
+
+    bool reachable(const Reach& r, const QN& q) const;
+    Reach make_reach(int a, int b) const;
+
+    dmrg_status set_order(const int32_t* ordering);
+    dmrg_status initialize(int D);
+    std::unique_ptr<Stored> vacuum(char side, int lo);
+    dmrg_status enlarge(const Stored& base, char side, const std::vector<QN>& allowed,
+                        Enl& en, OpSet& ops);
+    dmrg_status renormalize(const Enl& en, const OpSet& ops, bool normal_in, Stored& out,
+                            const std::vector<int>& keep_m, const std::vector<int>& kdim);
+    dmrg_status setup_bond(int b, std::unique_ptr<Bond>& out);
+    dmrg_status build_heff_plan(Bond& B);
+    dmrg_status build_diag(Bond& B);
+    dmrg_status heff(Bond& B, const double* x, double* y, int prec);
+    dmrg_status heff_launch(Bond& B, const double* x, double* y, int prec);
+    dmrg_status ensure_lo(Bond& B, int prec);
+    dmrg_status davidson(Bond& B, double* theta, int64_t* nlo, int64_t* n64, bool* conv);
+    dmrg_status truncate_and_move(int D, double alpha, double* disc);
+    dmrg_status density_matrix(Bond& B, bool left, double alpha, Buf& rho,
+                               std::vector<int64_t>& roff, std::vector<int>& rdim);
+    dmrg_status random_psi(Bond& B, Buf& out);
+    dmrg_status run_gemm(int prec, void* const* bufs, const GemmPlan& p, int cprec = -1);
+    dmrg_status ensure_dv(int64_t n, int kmax);
+    std::vector<std::vector<double>> selection_iso(const std::vector<int>& dims, int D, int tag,
+                                                   int pos, const std::vector<QN>& qs, bool mix,
+                                                   std::vector<int>& kept,
+                                                   std::vector<std::vector<int>>* chosen);
+};
+
+}  // namespace dm
