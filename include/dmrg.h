@@ -77,6 +77,12 @@ typedef struct dmrg_sweep_stats {
     double blocking_seconds;  /* wall time building enlarged-block operators and plans */
     int32_t status;           /* per-context status (dmrg_sweep_many) */
     int32_t steps;            /* two-site steps done */
+    /* per-kernel accounting of the H_eff.psi grouped GEMMs (HIP events on the
+     * context stream): phase 1 forms psi op(B)^T, phase 2 accumulates op(A) Z */
+    int64_t gemm1_launches, gemm2_launches;
+    double gemm1_seconds, gemm2_seconds;
+    double gemm1_flops, gemm2_flops;
+    double gemm1_bytes, gemm2_bytes;   /* algorithmic operand + result bytes */
 } dmrg_sweep_stats;
 
 typedef struct dmrg_ctx dmrg_ctx;

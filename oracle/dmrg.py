@@ -38,6 +38,7 @@ from __future__ import annotations
 
 import dataclasses
 import math
+import time
 from typing import Dict, List, Optional, Tuple
 
 import numpy as np
@@ -209,6 +210,8 @@ class DMRG:
         self.records: List[StepRecord] = []
         self.nprod_total = 0
         self.sweeps_done = 0
+        self.heff_flops = 0.0      # matmul flops of all H_eff products (timing report only)
+        self.heff_seconds = 0.0
 
     # ------------------------------------------------------------------ sectors
     def reach(self, a: int, b: int) -> set:
@@ -567,8 +570,10 @@ class DMRG:
         return terms
 
     def heff_apply(self, terms, psi: Dict[QN, np.ndarray]) -> Dict[QN, np.ndarray]:
+        t0 = time.perf_counter()
         T = self.T
         y = {q: np.zeros_like(b) for q, b in psi.items()}
+        flops = 0.0
         for coef, A, tA, B, tB, sign_out, par in terms:
             for q_in, X in psi.items():
                 if A is None:
@@ -590,9 +595,17 @@ class DMRG:
                 sg = 1.0
                 if par:
                     sg = -1.0 if nparticles(q_out if sign_out else q_in) % 2 else 1.0
-                Z = X if Bm is None else X @ Bm.T
-                Z = Z if Am is None else Am @ Z
+                if Bm is not None:
+                    flops += 2.0 * X.shape[0] * X.shape[1] * Bm.shape[0]
+                    Z = X @ Bm.T
+                else:
+                    Z = X
+                if Am is not None:
+                    flops += 2.0 * Am.shape[0] * Am.shape[1] * Z.shape[1]
+                    Z = Am @ Z
                 y[q_out] += (coef * sg) * Z
+        self.heff_flops += flops
+        self.heff_seconds += time.perf_counter() - t0
         return y
 
     def heff_diag(self, terms, psi) -> Dict[QN, np.ndarray]:

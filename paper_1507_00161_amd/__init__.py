@@ -41,7 +41,11 @@ class SweepStats(ctypes.Structure):
                 ("heff_flops", ctypes.c_double), ("heff_seconds", ctypes.c_double),
                 ("sweep_seconds", ctypes.c_double), ("renorm_seconds", ctypes.c_double),
                 ("blocking_seconds", ctypes.c_double), ("status", ctypes.c_int32),
-                ("steps", ctypes.c_int32)]
+                ("steps", ctypes.c_int32),
+                ("gemm1_launches", ctypes.c_int64), ("gemm2_launches", ctypes.c_int64),
+                ("gemm1_seconds", ctypes.c_double), ("gemm2_seconds", ctypes.c_double),
+                ("gemm1_flops", ctypes.c_double), ("gemm2_flops", ctypes.c_double),
+                ("gemm1_bytes", ctypes.c_double), ("gemm2_bytes", ctypes.c_double)]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}

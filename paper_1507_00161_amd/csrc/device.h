@@ -43,12 +43,23 @@ struct GemmChunk {
     int32_t lda, ldb, K;
     uint8_t a_buf, b_buf, a_trans, b_trans;
 };
+// c_local = 1: C is a compact 64 x 64 partial tile at c_off (row stride
+// kTileN, indexed from the tile origin) instead of the output block.
 struct GemmTask {
     int64_t c_off;
     int32_t ldc, m0, n0, mt, nt;
     int32_t chunk_begin, chunk_end;
-    uint8_t c_buf, beta, pad0, pad1;
+    uint8_t c_buf, beta, c_local, pad1;
 };
+// Split-K reduction: dst tile (mt x nt at dst_off, row stride ld) =
+// (beta ? dst : 0) + sum of nslots consecutive partial tiles from slot0,
+// summed in slot order (deterministic).
+struct RedTask {
+    int64_t dst_off;
+    int32_t ld, mt, nt, slot0, nslots;
+    uint8_t dst_buf, beta, pad0, pad1;
+};
+constexpr int kPartialBuf = 7;   // buffer index of the partial tiles
 constexpr int kTileM = 64;
 constexpr int kTileN = 64;
 
@@ -59,6 +70,7 @@ enum Prec { P_F64 = 0, P_F32 = 1, P_BF16 = 2 };
 // for F64 operands and FP32 otherwise.
 int gemm(Ctx* c, int ab_prec, int c_prec, void* const* bufs, const GemmTask* d_tasks, int ntasks,
          const GemmChunk* d_chunks);
+int gemm_reduce(Ctx* c, int c_prec, void* const* bufs, const RedTask* d_tasks, int ntasks);
 
 // ------------------------------------------------------- linear combination
 // dst[r0+r, c0+c] = sum_terms coef * src(r0+r, c0+c) with src(r, c) =
@@ -111,7 +123,8 @@ int precond(Ctx* c, const double* r, const double* d, const double* d_theta, int
 int scale_inv_norm(Ctx* c, double* x, int64_t n, const double* d_norm2);
 // y = x * (1/sqrt(*d_norm2))
 int copy_scaled_inv_norm(Ctx* c, const double* x, int64_t n, const double* d_norm2, double* y);
-// lowest eigenpair of the symmetrised k x k matrix (G + G^T)/2, row stride ldg
+// lowest eigenpair of the symmetric k x k matrix whose lower triangle
+// (G[i][j], j <= i) is given at row stride ldg
 int small_eigh(Ctx* c, const double* d_G, int k, int ldg, double* d_theta, double* d_s);
 // type conversion of n elements
 int convert(Ctx* c, int from_prec, const void* src, int to_prec, void* dst, int64_t n);

@@ -209,69 +209,65 @@ template <> struct MmaTraits<float> {
     static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane >> 4) + r; }
 };
 
-template <class T>
-__device__ __forceinline__ void stage_a(T* __restrict__ As, const T* __restrict__ A, const GemmChunk& ch,
-                                        int m0, int mt, int k0, T alpha, int tid) {
-    constexpr int BK = 16, LDA_S = TM + 1;
-    if (!ch.a_trans) {
-        // A row-major M x K: thread -> row tid/4, k 4*(tid%4)..+3
-        int m = tid >> 2, kk = (tid & 3) * 4;
-        const T* src = A + (int64_t)(m0 + m) * ch.lda + k0 + kk;
+// Register staging of one K slice (E = BK*64/256 elements per thread).
+// Two access patterns: "along K" (the operand is stored with K contiguous:
+// A non-transposed, B transposed) and "along M/N" (A transposed, B plain).
+template <class T, int BK>
+struct Slice {
+    static constexpr int E = BK * 64 / NTH;
+    T v[E];
+    // operand stored row-major with K contiguous: element (r, k) at P[r*ld + k]
+    __device__ __forceinline__ void load_k(const T* __restrict__ P, int ld, int r0, int rmax, int k0, int K,
+                                           T scale, int tid) {
+        const int r = tid >> 2, kk = (tid & 3) * E;
+        const T* src = P + (int64_t)(r0 + r) * ld + k0 + kk;
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            int k = k0 + kk + u;
-            T v = (m < mt && k < ch.K) ? src[u] : T(0);
-            As[(kk + u) * LDA_S + m] = v * alpha;
-        }
-    } else {
-        // A stored K x M: thread -> k tid/16, m 4*(tid%16)..+3
-        int kk = tid >> 4, m = (tid & 15) * 4;
-        int k = k0 + kk;
-        const T* src = A + (int64_t)k * ch.lda + m0 + m;
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            T v = (m + u < mt && k < ch.K) ? src[u] : T(0);
-            As[kk * LDA_S + m + u] = v * alpha;
-        }
+        for (int u = 0; u < E; ++u) v[u] = (r < rmax && k0 + kk + u < K) ? src[u] * scale : T(0);
     }
-    (void)BK;
+    // operand stored row-major with M (or N) contiguous: element (r, k) at P[k*ld + r]
+    __device__ __forceinline__ void load_m(const T* __restrict__ P, int ld, int r0, int rmax, int k0, int K,
+                                           T scale, int tid) {
+        constexpr int TPR = 64 / E;   // threads per k row
+        const int kk = tid / TPR, r = (tid % TPR) * E;
+        const T* src = P + (int64_t)(k0 + kk) * ld + r0 + r;
+#pragma unroll
+        for (int u = 0; u < E; ++u) v[u] = (r + u < rmax && k0 + kk < K) ? src[u] * scale : T(0);
+    }
+    // LDS tile S[k][r] with row stride LD
+    template <int LD>
+    __device__ __forceinline__ void store_k(T* __restrict__ S, int tid) const {
+        const int r = tid >> 2, kk = (tid & 3) * E;
+#pragma unroll
+        for (int u = 0; u < E; ++u) S[(kk + u) * LD + r] = v[u];
+    }
+    template <int LD>
+    __device__ __forceinline__ void store_m(T* __restrict__ S, int tid) const {
+        constexpr int TPR = 64 / E;
+        const int kk = tid / TPR, r = (tid % TPR) * E;
+#pragma unroll
+        for (int u = 0; u < E; ++u) S[kk * LD + r + u] = v[u];
+    }
+};
+
+// Work-groups are dispatched round-robin over the 8 XCDs; map consecutive
+// tasks (tiles of one output block, which share operands) to one XCD so
+// that they meet in the same L2.  The grid is padded to a multiple of 8.
+__device__ __forceinline__ int xcd_task(int ntasks) {
+    const int per = (ntasks + 7) >> 3;
+    const int b = blockIdx.x;
+    return (b & 7) * per + (b >> 3);
 }
 
-template <class T>
-__device__ __forceinline__ void stage_b(T* __restrict__ Bs, const T* __restrict__ B, const GemmChunk& ch,
-                                        int n0, int nt, int k0, int tid) {
-    constexpr int LDB_S = TN + 1;
-    if (!ch.b_trans) {
-        // B row-major K x N: thread -> k tid/16, n 4*(tid%16)..+3
-        int kk = tid >> 4, n = (tid & 15) * 4;
-        int k = k0 + kk;
-        const T* src = B + (int64_t)k * ch.ldb + n0 + n;
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            T v = (n + u < nt && k < ch.K) ? src[u] : T(0);
-            Bs[kk * LDB_S + n + u] = v;
-        }
-    } else {
-        // B stored N x K: thread -> n tid/4, k 4*(tid%4)..+3
-        int n = tid >> 2, kk = (tid & 3) * 4;
-        const T* src = B + (int64_t)(n0 + n) * ch.ldb + k0 + kk;
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            int k = k0 + kk + u;
-            T v = (n < nt && k < ch.K) ? src[u] : T(0);
-            Bs[(kk + u) * LDB_S + n] = v;
-        }
-    }
-}
-
-template <class T, class TC>
+template <class T, class TC, int BK>
 __global__ void __launch_bounds__(NTH) k_gemm(Bufs bufs, const GemmTask* __restrict__ tasks,
-                                              const GemmChunk* __restrict__ chunks) {
+                                              const GemmChunk* __restrict__ chunks, int ntasks) {
     typedef typename MmaTraits<T>::acc_t acc_t;
-    constexpr int BK = 16, LDA_S = TM + 1, LDB_S = TN + 1;
-    __shared__ T As[BK * LDA_S];
-    __shared__ T Bs[BK * LDB_S];
-    const GemmTask tk = tasks[blockIdx.x];
+    constexpr int LDA = TM + 16, LDB = TN + 16;   // padding: lane groups hit distinct LDS banks
+    __shared__ T As[2][BK * LDA];
+    __shared__ T Bs[2][BK * LDB];
+    const int ti = xcd_task(ntasks);
+    if (ti >= ntasks) return;
+    const GemmTask tk = tasks[ti];
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63;
     const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;   // wave quadrant
@@ -280,33 +276,69 @@ __global__ void __launch_bounds__(NTH) k_gemm(Bufs bufs, const GemmTask* __restr
     for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b) acc[a][b] = acc_t{0, 0, 0, 0};
-    for (int c = tk.chunk_begin; c < tk.chunk_end; ++c) {
-        const GemmChunk ch = chunks[c];
+    Slice<T, BK> ra, rb;
+    auto load = [&](const GemmChunk& ch, int k0) {
         const T* A = (const T*)bufs.p[ch.a_buf] + ch.a_off;
         const T* B = (const T*)bufs.p[ch.b_buf] + ch.b_off;
         const T alpha = (T)ch.alpha;
-        for (int k0 = 0; k0 < ch.K; k0 += BK) {
-            stage_a<T>(As, A, ch, tk.m0, tk.mt, k0, alpha, tid);
-            stage_b<T>(Bs, B, ch, tk.n0, tk.nt, k0, tid);
-            __syncthreads();
+        if (!ch.a_trans) ra.load_k(A, ch.lda, tk.m0, tk.mt, k0, ch.K, alpha, tid);
+        else ra.load_m(A, ch.lda, tk.m0, tk.mt, k0, ch.K, alpha, tid);
+        if (!ch.b_trans) rb.load_m(B, ch.ldb, tk.n0, tk.nt, k0, ch.K, T(1), tid);
+        else rb.load_k(B, ch.ldb, tk.n0, tk.nt, k0, ch.K, T(1), tid);
+    };
+    auto store = [&](const GemmChunk& ch, int buf) {
+        if (!ch.a_trans) ra.template store_k<LDA>(As[buf], tid);
+        else ra.template store_m<LDA>(As[buf], tid);
+        if (!ch.b_trans) rb.template store_m<LDB>(Bs[buf], tid);
+        else rb.template store_k<LDB>(Bs[buf], tid);
+    };
+    int c = tk.chunk_begin;
+    if (c < tk.chunk_end) {
+        GemmChunk ch = chunks[c];
+        int k0 = 0;
+        load(ch, k0);
+        store(ch, 0);
+        __syncthreads();
+        int buf = 0;
+        while (true) {
+            // next slice: same chunk or the next one
+            int nc = c, nk0 = k0 + BK;
+            GemmChunk nch = ch;
+            if (nk0 >= ch.K) {
+                nc = c + 1;
+                nk0 = 0;
+                if (nc < tk.chunk_end) nch = chunks[nc];
+            }
+            const bool more = nc < tk.chunk_end;
+            if (more) load(nch, nk0);   // global loads in flight during the MFMAs
+            const T* Ab = As[buf];
+            const T* Bb = Bs[buf];
 #pragma unroll
             for (int ks = 0; ks < BK; ks += 4) {
                 const int kr = ks + (lane >> 4);
                 T av[2], bv[2];
 #pragma unroll
-                for (int a = 0; a < 2; ++a) av[a] = As[kr * LDA_S + wm + a * 16 + (lane & 15)];
+                for (int a = 0; a < 2; ++a) av[a] = Ab[kr * LDA + wm + a * 16 + (lane & 15)];
 #pragma unroll
-                for (int b = 0; b < 2; ++b) bv[b] = Bs[kr * LDB_S + wn + b * 16 + (lane & 15)];
+                for (int b = 0; b < 2; ++b) bv[b] = Bb[kr * LDB + wn + b * 16 + (lane & 15)];
 #pragma unroll
                 for (int a = 0; a < 2; ++a)
 #pragma unroll
                     for (int b = 0; b < 2; ++b) acc[a][b] = MmaTraits<T>::mma(av[a], bv[b], acc[a][b]);
             }
+            if (more) store(nch, buf ^ 1);
             __syncthreads();
+            if (!more) break;
+            c = nc;
+            k0 = nk0;
+            ch = nch;
+            buf ^= 1;
         }
     }
     // epilogue
     TC* C = (TC*)bufs.p[tk.c_buf] + tk.c_off;
+    const int64_t ldc = tk.c_local ? TN : tk.ldc;
+    const int64_t base = tk.c_local ? 0 : (int64_t)tk.m0 * tk.ldc + tk.n0;
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -316,7 +348,7 @@ __global__ void __launch_bounds__(NTH) k_gemm(Bufs bufs, const GemmTask* __restr
                 int row = wm + a * 16 + MmaTraits<T>::row(lane, r);
                 int col = wn + b * 16 + (lane & 15);
                 if (row < tk.mt && col < tk.nt) {
-                    TC* dst = C + (int64_t)(tk.m0 + row) * tk.ldc + tk.n0 + col;
+                    TC* dst = C + base + (int64_t)row * ldc + col;
                     double v = (double)acc[a][b][r];
                     if (tk.beta) v += (double)*dst;
                     *dst = (TC)v;
@@ -377,11 +409,13 @@ __device__ __forceinline__ void stage_b_bf(bf16_t* __restrict__ Bs, const bf16_t
 
 template <class TC>
 __global__ void __launch_bounds__(NTH) k_gemm_bf16(Bufs bufs, const GemmTask* __restrict__ tasks,
-                                                   const GemmChunk* __restrict__ chunks) {
+                                                   const GemmChunk* __restrict__ chunks, int ntasks) {
     constexpr int BK = 32, LDS = BK + 8;
     __shared__ __attribute__((aligned(16))) bf16_t As[TM * LDS];
     __shared__ __attribute__((aligned(16))) bf16_t Bs[TN * LDS];
-    const GemmTask tk = tasks[blockIdx.x];
+    const int ti = xcd_task(ntasks);
+    if (ti >= ntasks) return;
+    const GemmTask tk = tasks[ti];
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63;
     const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
@@ -417,6 +451,8 @@ __global__ void __launch_bounds__(NTH) k_gemm_bf16(Bufs bufs, const GemmTask* __
         }
     }
     TC* C = (TC*)bufs.p[tk.c_buf] + tk.c_off;
+    const int64_t ldc = tk.c_local ? TN : tk.ldc;
+    const int64_t base = tk.c_local ? 0 : (int64_t)tk.m0 * tk.ldc + tk.n0;
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -426,7 +462,7 @@ __global__ void __launch_bounds__(NTH) k_gemm_bf16(Bufs bufs, const GemmTask* __
                 int row = wm + a * 16 + 4 * (lane >> 4) + r;
                 int col = wn + b * 16 + (lane & 15);
                 if (row < tk.mt && col < tk.nt) {
-                    TC* dst = C + (int64_t)(tk.m0 + row) * tk.ldc + tk.n0 + col;
+                    TC* dst = C + base + (int64_t)row * ldc + col;
                     float v = acc[a][b][r];
                     if constexpr (sizeof(TC) == 4) {
                         if (tk.beta) v += *(float*)dst;
@@ -443,17 +479,50 @@ int gemm(Ctx* c, int ab, int cp, void* const* bufs, const GemmTask* tasks, int n
     if (ntasks <= 0) return 0;
     Bufs b;
     for (int i = 0; i < kMaxBufs; ++i) b.p[i] = bufs[i];
-    dim3 grid(ntasks), block(NTH);
+    dim3 grid(((ntasks + 7) / 8) * 8), block(NTH);
     if (ab == P_F64 && cp == P_F64)
-        hipLaunchKernelGGL((k_gemm<double, double>), grid, block, 0, c->stream, b, tasks, chunks);
+        hipLaunchKernelGGL((k_gemm<double, double, 16>), grid, block, 0, c->stream, b, tasks, chunks, ntasks);
     else if (ab == P_F32 && cp == P_F32)
-        hipLaunchKernelGGL((k_gemm<float, float>), grid, block, 0, c->stream, b, tasks, chunks);
+        hipLaunchKernelGGL((k_gemm<float, float, 32>), grid, block, 0, c->stream, b, tasks, chunks, ntasks);
     else if (ab == P_BF16 && cp == P_F32)
-        hipLaunchKernelGGL((k_gemm_bf16<float>), grid, block, 0, c->stream, b, tasks, chunks);
+        hipLaunchKernelGGL((k_gemm_bf16<float>), grid, block, 0, c->stream, b, tasks, chunks, ntasks);
     else if (ab == P_BF16 && cp == P_BF16)
-        hipLaunchKernelGGL((k_gemm_bf16<bf16_t>), grid, block, 0, c->stream, b, tasks, chunks);
+        hipLaunchKernelGGL((k_gemm_bf16<bf16_t>), grid, block, 0, c->stream, b, tasks, chunks, ntasks);
     else {
         c->err = "unsupported GEMM precision combination";
+        return 1;
+    }
+    LAUNCHCHK(c);
+    return 0;
+}
+
+// ------------------------------------------------------ split-K reduction
+template <class TC>
+__global__ void __launch_bounds__(256) k_gemm_reduce(Bufs bufs, const RedTask* __restrict__ tasks) {
+    const RedTask tk = tasks[blockIdx.x];
+    const TC* P = (const TC*)bufs.p[kPartialBuf] + (int64_t)tk.slot0 * TM * TN;
+    TC* D = (TC*)bufs.p[tk.dst_buf] + tk.dst_off;
+    for (int e = threadIdx.x; e < TM * TN; e += blockDim.x) {
+        const int r = e / TN, c = e % TN;
+        if (r >= tk.mt || c >= tk.nt) continue;
+        double s = 0.0;
+        for (int q = 0; q < tk.nslots; ++q) s += (double)P[(int64_t)q * TM * TN + e];
+        TC* d = D + (int64_t)r * tk.ld + c;
+        if (tk.beta) s += (double)*d;
+        *d = (TC)s;
+    }
+}
+
+int gemm_reduce(Ctx* c, int cp, void* const* bufs, const RedTask* tasks, int ntasks) {
+    if (ntasks <= 0) return 0;
+    Bufs b;
+    for (int i = 0; i < kMaxBufs; ++i) b.p[i] = bufs[i];
+    if (cp == P_F64)
+        hipLaunchKernelGGL(k_gemm_reduce<double>, dim3(ntasks), dim3(256), 0, c->stream, b, tasks);
+    else if (cp == P_F32)
+        hipLaunchKernelGGL(k_gemm_reduce<float>, dim3(ntasks), dim3(256), 0, c->stream, b, tasks);
+    else {
+        c->err = "split-K reduction supports FP64 and FP32 outputs";
         return 1;
     }
     LAUNCHCHK(c);
@@ -688,7 +757,7 @@ __global__ void __launch_bounds__(64) k_small_eigh(const double* __restrict__ G,
     for (int e = t; e < 32 * 32; e += 64) {
         int i = e >> 5, j = e & 31;
         double v = 0.0;
-        if (i < k && j < k) v = 0.5 * (G[i * ldg + j] + G[j * ldg + i]);
+        if (i < k && j < k) v = i >= j ? G[i * ldg + j] : G[j * ldg + i];
         A[i][j] = v;
         Vm[i][j] = i == j ? 1.0 : 0.0;
     }

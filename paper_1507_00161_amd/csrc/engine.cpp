@@ -115,11 +115,21 @@ Engine::~Engine() {
     } while (0)
 
 // ------------------------------------------------------ GEMM plan builder
+// Output blocks with their chunk lists are collected first; `finish_plan`
+// then tiles them (64 x 64) and splits a tile's chunk list over several
+// work-groups when the plan has fewer tiles than the chip has room for
+// (split-K into partial tiles, reduced in a fixed order by a second kernel).
 struct GB {
-    std::vector<GemmTask> tasks;
+    struct OB {
+        int cbuf;
+        int64_t coff;
+        int ldc, M, Nn, beta;
+        int64_t cb, ce;
+    };
+    std::vector<OB> obs;
     std::vector<GemmChunk> chunks;
     int64_t cb = 0;
-    double flops = 0.0;
+    double flops = 0.0, elems = 0.0;
     void begin() { cb = (int64_t)chunks.size(); }
     void chunk(double alpha, int abuf, int64_t aoff, int lda, bool atr, int bbuf, int64_t boff, int ldb,
                bool btr, int K) {
@@ -138,38 +148,126 @@ struct GB {
     }
     void end(int cbuf, int64_t coff, int ldc, int M, int Nn, int beta) {
         int64_t ce = (int64_t)chunks.size();
-        for (int64_t x = cb; x < ce; ++x) flops += 2.0 * M * Nn * chunks[x].K;
-        for (int m0 = 0; m0 < M; m0 += dmrgdev::kTileM)
-            for (int n0 = 0; n0 < Nn; n0 += dmrgdev::kTileN) {
-                GemmTask t;
-                t.c_off = coff;
-                t.ldc = ldc;
-                t.m0 = m0;
-                t.n0 = n0;
-                t.mt = std::min(dmrgdev::kTileM, M - m0);
-                t.nt = std::min(dmrgdev::kTileN, Nn - n0);
-                t.chunk_begin = (int32_t)cb;
-                t.chunk_end = (int32_t)ce;
-                t.c_buf = (uint8_t)cbuf;
-                t.beta = (uint8_t)beta;
-                t.pad0 = t.pad1 = 0;
-                tasks.push_back(t);
-            }
+        for (int64_t x = cb; x < ce; ++x) {
+            flops += 2.0 * M * Nn * chunks[x].K;
+            elems += (double)chunks[x].K * (M + Nn);
+        }
+        elems += (double)M * Nn * (beta ? 2 : 1);
+        obs.push_back({cbuf, coff, ldc, M, Nn, beta, cb, ce});
     }
 };
 
-dmrg_status Engine::run_gemm(int prec, void* const* bufs, const GemmPlan& p, int cprec) {
+dmrg_status Engine::run_gemm(int prec, BufTable bufs, const GemmPlan& p, int cprec) {
     if (p.ntasks == 0) return DMRG_OK;
     if (cprec < 0) cprec = prec == dmrgdev::P_BF16 ? dmrgdev::P_F32 : prec;
-    DEV(dmrgdev::gemm(dev_, prec, cprec, bufs, p.tasks.as<GemmTask>(), p.ntasks, p.chunks.as<GemmChunk>()));
+    if (p.nslots) {
+        TRY(ensure_partials(p.nslots));
+        bufs[dmrgdev::kPartialBuf] = partial_.p;
+    }
+    DEV(dmrgdev::gemm(dev_, prec, cprec, bufs.data(), p.tasks.as<GemmTask>(), p.ntasks, p.chunks.as<GemmChunk>()));
+    if (p.nreds)
+        DEV(dmrgdev::gemm_reduce(dev_, cprec, bufs.data(), p.reds.as<dmrgdev::RedTask>(), p.nreds));
     return DMRG_OK;
 }
 
+dmrg_status Engine::ensure_partials(int64_t slots) {
+    size_t need = (size_t)slots * dmrgdev::kTileM * dmrgdev::kTileN * sizeof(double);
+    if (partial_.bytes >= need) return DMRG_OK;
+    return alloc_buf(partial_, need);
+}
+
 static dmrg_status finish_plan(Engine& e, GB& g, GemmPlan& p) {
-    p.ntasks = (int)g.tasks.size();
+    using dmrgdev::kTileM;
+    using dmrgdev::kTileN;
+    std::vector<GemmTask> tasks;
+    std::vector<dmrgdev::RedTask> reds;
+    // total work in K units, tile by tile
+    double work = 0.0;
+    int64_t ntiles = 0;
+    for (const auto& ob : g.obs) {
+        double kk = 0.0;
+        for (int64_t c = ob.cb; c < ob.ce; ++c) kk += g.chunks[c].K;
+        int64_t nt = (int64_t)((ob.M + kTileM - 1) / kTileM) * ((ob.Nn + kTileN - 1) / kTileN);
+        work += kk * nt;
+        ntiles += nt;
+    }
+    const double target = 2048.0;   // work-groups that keep 256 CUs busy
+    const double kper = std::max(work / target, 1024.0);
+    int64_t slot = 0;
+    for (const auto& ob : g.obs) {
+        double kk = 0.0;
+        for (int64_t c = ob.cb; c < ob.ce; ++c) kk += g.chunks[c].K;
+        int parts = (int)std::min(64.0, std::max(1.0, std::ceil(kk / kper)));
+        if (ob.ce - ob.cb < 2) parts = 1;
+        // chunk ranges of the parts (balanced by K)
+        std::vector<std::pair<int64_t, int64_t>> ranges;
+        if (parts == 1) {
+            ranges.push_back({ob.cb, ob.ce});
+        } else {
+            double run = 0.0;
+            int64_t start = ob.cb;
+            int q = 1;
+            for (int64_t c = ob.cb; c < ob.ce; ++c) {
+                run += g.chunks[c].K;
+                if (run >= kk * q / parts && c + 1 < ob.ce) {
+                    ranges.push_back({start, c + 1});
+                    start = c + 1;
+                    ++q;
+                }
+            }
+            if (start < ob.ce) ranges.push_back({start, ob.ce});
+        }
+        for (int m0 = 0; m0 < ob.M; m0 += kTileM)
+            for (int n0 = 0; n0 < ob.Nn; n0 += kTileN) {
+                GemmTask t{};
+                t.ldc = ob.ldc;
+                t.m0 = m0;
+                t.n0 = n0;
+                t.mt = std::min(kTileM, ob.M - m0);
+                t.nt = std::min(kTileN, ob.Nn - n0);
+                if (ranges.size() == 1) {
+                    t.c_off = ob.coff;
+                    t.chunk_begin = (int32_t)ranges[0].first;
+                    t.chunk_end = (int32_t)ranges[0].second;
+                    t.c_buf = (uint8_t)ob.cbuf;
+                    t.beta = (uint8_t)ob.beta;
+                    t.c_local = 0;
+                    tasks.push_back(t);
+                    continue;
+                }
+                dmrgdev::RedTask r{};
+                r.dst_off = ob.coff + (int64_t)m0 * ob.ldc + n0;
+                r.ld = ob.ldc;
+                r.mt = t.mt;
+                r.nt = t.nt;
+                r.slot0 = (int32_t)slot;
+                r.nslots = (int32_t)ranges.size();
+                r.dst_buf = (uint8_t)ob.cbuf;
+                r.beta = (uint8_t)ob.beta;
+                reds.push_back(r);
+                for (auto& rg : ranges) {
+                    GemmTask u = t;
+                    u.c_off = slot * (int64_t)kTileM * kTileN;
+                    u.chunk_begin = (int32_t)rg.first;
+                    u.chunk_end = (int32_t)rg.second;
+                    u.c_buf = (uint8_t)dmrgdev::kPartialBuf;
+                    u.beta = 0;
+                    u.c_local = 1;
+                    tasks.push_back(u);
+                    ++slot;
+                }
+            }
+    }
+    (void)ntiles;
+    p.ntasks = (int)tasks.size();
+    p.nreds = (int)reds.size();
+    p.nslots = slot;
     p.nchunks = (int64_t)g.chunks.size();
     p.flops = g.flops;
-    dmrg_status st = e.upload(p.tasks, g.tasks);
+    p.elems = g.elems;
+    dmrg_status st = e.upload(p.tasks, tasks);
+    if (st) return st;
+    st = e.upload(p.reds, reds);
     if (st) return st;
     return e.upload(p.chunks, g.chunks);
 }
@@ -841,7 +939,7 @@ dmrg_status Engine::renormalize(const Enl& en, const OpSet& ops, bool normal_in,
     GemmPlan p1, p2;
     TRY(finish_plan(*this, g1, p1));
     TRY(finish_plan(*this, g2, p2));
-    void* bufs[5] = {ops.pool.p, out.iso.p, tbuf.p, out.ops.pool.p, tmp.pool.p};
+    BufTable bufs{ops.pool.p, out.iso.p, tbuf.p, out.ops.pool.p, tmp.pool.p};
     TRY(run_gemm(dmrgdev::P_F64, bufs, p1));
     TRY(run_gemm(dmrgdev::P_F64, bufs, p2));
     DEV(dmrgdev::sync(dev_));
@@ -1128,12 +1226,6 @@ dmrg_status Engine::build_heff_plan(Bond& B) {
             g2.end(4, yoff, ldy, S.sub[o.i].dim, E.sub[o.j].dim, first ? 0 : 1);
             l.clear();
         }
-#ifdef DMRG_DEBUG
-        for (auto& tk : g2.tasks) {
-            fprintf(stderr, "  P2 task c_off=%lld ldc=%d m0=%d n0=%d mt=%d nt=%d chunks %d..%d beta=%d\n", (long long)tk.c_off, tk.ldc, tk.m0, tk.n0, tk.mt, tk.nt, tk.chunk_begin, tk.chunk_end, tk.beta);
-            for (int c = tk.chunk_begin; c < tk.chunk_end; ++c) { auto& k = g2.chunks[c]; fprintf(stderr, "     ch a=%d:%lld lda=%d tr=%d b=%d:%lld ldb=%d tr=%d K=%d alpha=%g\n", k.a_buf, (long long)k.a_off, k.lda, k.a_trans, k.b_buf, (long long)k.b_off, k.ldb, k.b_trans, k.K, k.alpha); }
-        }
-#endif
         TRY(finish_plan(*this, g1, grp.p1));
         TRY(finish_plan(*this, g2, grp.p2));
         B.flops += grp.p1.flops + grp.p2.flops;
@@ -1160,21 +1252,6 @@ dmrg_status Engine::build_heff_plan(Bond& B) {
         z += w.zsize;
     }
     TRY(close_group());
-#ifdef DMRG_DEBUG
-    fprintf(stderr, "bond %d: %zu terms, %d psi blocks, dim %lld\n", B.b, B.terms.size(), nb, (long long)B.dim);
-    for (size_t t = 0; t < B.terms.size(); ++t) {
-        const Term& tm = B.terms[t];
-        fprintf(stderr, "  term %zu a=%d(%c%d,%d) ta=%d b=%d(%c%d,%d) tb=%d so=%d par=%d\n", t, tm.a,
-                tm.a >= 0 ? B.Sops.keys[tm.a].k : '-', tm.a >= 0 ? B.Sops.keys[tm.a].i : 0, tm.a >= 0 ? B.Sops.keys[tm.a].j : 0, tm.ta, tm.b,
-                tm.b >= 0 ? B.Eops.keys[tm.b].k : '-', tm.b >= 0 ? B.Eops.keys[tm.b].i : 0, tm.b >= 0 ? B.Eops.keys[tm.b].j : 0, tm.tb, tm.sign_out, tm.par);
-    }
-    for (size_t o = 0; o < B.Eops.ops.size(); ++o) {
-        fprintf(stderr, "  Eop %c%d,%d:", B.Eops.keys[o].k, B.Eops.keys[o].i, B.Eops.keys[o].j);
-        for (auto& b : B.Eops.ops[o].blk) fprintf(stderr, " (%d<-%d %dx%d)", b.out, b.in, b.rows, b.cols);
-        fprintf(stderr, "\n");
-    }
-    for (size_t j = 0; j < E.sub.size(); ++j) fprintf(stderr, "  Esub %zu m=%d base=%d sg=%d off=%d dim=%d\n", j, E.sub[j].m, E.sub[j].base, E.sub[j].sigma, E.sub[j].off, E.sub[j].dim);
-#endif
     int64_t zmax = 0;
     for (auto& g : B.groups) zmax = std::max(zmax, g.z_elems);
     if ((int64_t)(z_.bytes / sizeof(double)) < zmax)
@@ -1260,37 +1337,68 @@ dmrg_status Engine::ensure_lo(Bond& B, int prec) {
 // y = H_eff x (device pointers, FP64 I/O)
 dmrg_status Engine::heff(Bond& B, const double* x, double* y, int prec) {
     DEV(dmrgdev::event_record(dev_, 0));
-    TRY(heff_launch(B, x, y, prec));
+    TRY(heff_launch(B, x, y, prec, true));
     DEV(dmrgdev::event_record(dev_, 1));
     heff_time_ += dmrgdev::event_elapsed(dev_, 0, 1);
     return DMRG_OK;
 }
 
-dmrg_status Engine::heff_launch(Bond& B, const double* x, double* y, int prec) {
+// one product with per-phase event timing (the events add no synchronisation;
+// the elapsed times are read after the product completes)
+dmrg_status Engine::heff_launch(Bond& B, const double* x, double* y, int prec, bool timed) {
+    const double es = prec == dmrgdev::P_F64 ? 8.0 : (prec == dmrgdev::P_F32 ? 4.0 : 2.0);
     if (prec == dmrgdev::P_F64) {
         for (size_t g = 0; g < B.groups.size(); ++g) {
-            void* bufs[5] = {B.Sops.pool.p, B.Eops.pool.p, (void*)x, z_.p, y};
+            BufTable bufs{B.Sops.pool.p, B.Eops.pool.p, (void*)x, z_.p, y};
+            if (timed) DEV(dmrgdev::event_record(dev_, 2));
             TRY(run_gemm(prec, bufs, B.groups[g].p1));
+            if (timed) DEV(dmrgdev::event_record(dev_, 3));
             TRY(run_gemm(prec, bufs, B.groups[g].p2));
+            if (timed) {
+                DEV(dmrgdev::event_record(dev_, 4));
+                account(B.groups[g], es, es);
+            }
         }
         return DMRG_OK;
     }
     TRY(ensure_lo(B, prec));
-    size_t es = prec == dmrgdev::P_F32 ? 4 : 2;
+    const size_t esz = prec == dmrgdev::P_F32 ? 4 : 2;
     int64_t zmax = 0;
     for (auto& g : B.groups) zmax = std::max(zmax, g.z_elems);
-    if (xlo_.bytes < (size_t)B.dim * es) TRY(alloc_buf(xlo_, std::max<int64_t>(B.dim, 1) * es));
+    if (xlo_.bytes < (size_t)B.dim * esz) TRY(alloc_buf(xlo_, std::max<int64_t>(B.dim, 1) * esz));
     if (ylo_.bytes < (size_t)B.dim * 4) TRY(alloc_buf(ylo_, std::max<int64_t>(B.dim, 1) * 4));
-    size_t zbytes = (size_t)std::max<int64_t>(zmax, 1) * es;
+    size_t zbytes = (size_t)std::max<int64_t>(zmax, 1) * esz;
     if (scr_a_.bytes < zbytes) TRY(alloc_buf(scr_a_, zbytes));
     DEV(dmrgdev::convert(dev_, dmrgdev::P_F64, x, prec, xlo_.p, B.dim));
     for (size_t g = 0; g < B.groups.size(); ++g) {
-        void* bufs[5] = {B.Sops.pool_lo.p, B.Eops.pool_lo.p, xlo_.p, scr_a_.p, ylo_.p};
+        BufTable bufs{B.Sops.pool_lo.p, B.Eops.pool_lo.p, xlo_.p, scr_a_.p, ylo_.p};
+        if (timed) DEV(dmrgdev::event_record(dev_, 2));
         TRY(run_gemm(prec, bufs, B.groups[g].p1, prec));          // Z in the operand precision
+        if (timed) DEV(dmrgdev::event_record(dev_, 3));
         TRY(run_gemm(prec, bufs, B.groups[g].p2, dmrgdev::P_F32));
+        if (timed) {
+            DEV(dmrgdev::event_record(dev_, 4));
+            account(B.groups[g], es, es);
+        }
     }
     DEV(dmrgdev::convert(dev_, dmrgdev::P_F32, ylo_.p, dmrgdev::P_F64, y, B.dim));
     return DMRG_OK;
+}
+
+void Engine::account(const HeffGroup& g, double es1, double es2) {
+    double t1 = dmrgdev::event_elapsed(dev_, 2, 3), t2 = dmrgdev::event_elapsed(dev_, 3, 4);
+    if (g.p1.ntasks) {
+        acc_.gemm1_launches += 1;
+        acc_.gemm1_seconds += t1;
+        acc_.gemm1_flops += g.p1.flops;
+        acc_.gemm1_bytes += g.p1.elems * es1;
+    }
+    if (g.p2.ntasks) {
+        acc_.gemm2_launches += 1;
+        acc_.gemm2_seconds += t2;
+        acc_.gemm2_flops += g.p2.flops;
+        acc_.gemm2_bytes += g.p2.elems * es2;
+    }
 }
 
 // =============================================================== Davidson
@@ -1311,11 +1419,16 @@ dmrg_status Engine::ensure_dv(int64_t n, int kmax) {
 // Lowest eigenpair of H_eff from the guess in psi_: subspace V from the
 // normalised guess; correction r / (diag - theta) (|diag - theta| >= 1e-12);
 // classical Gram-Schmidt twice; restart to [x] at the maximum subspace;
-// converged when |H x - theta x| <= tol.  In the mixed modes expansion
-// products run in reduced precision and, once the residual of the
-// reduced-precision problem stalls (or passes the tolerance), the subspace is
-// restarted from [x, H64 x] with an FP64 product, so that the accepted residual
-// and the reported energy are FP64 quantities.
+// converged when |H x - theta x| <= tol.
+//
+// Mixed modes (FP64 residual correction): expansion products run in reduced
+// precision; the subspace is periodically "refreshed" to [x] with an FP64
+// product H64 x.  Right after a refresh the residual and theta are FP64
+// quantities, and only then is convergence accepted.  Later reduced-precision
+// directions enter with weights of the order of the remaining error, so their
+// product error is second order and the iteration keeps converging.  A solve
+// starts with a refresh (one FP64 product), so a state that is already
+// converged costs a single FP64 product.
 dmrg_status Engine::davidson(Bond& B, double* theta_out, int64_t* nlo, int64_t* n64, bool* conv) {
     const int64_t n = B.dim;
     const int kmax = std::max(2, std::min(32, opt_.davidson_max_subspace));
@@ -1329,20 +1442,26 @@ dmrg_status Engine::davidson(Bond& B, double* theta_out, int64_t* nlo, int64_t* 
     const int ldg = 32;
     const int lowp = opt_.precision == DMRG_MIXED_FP32 ? dmrgdev::P_F32
                      : opt_.precision == DMRG_MIXED_BF16 ? dmrgdev::P_BF16 : dmrgdev::P_F64;
-    bool in_low = lowp != dmrgdev::P_F64;
+    const bool mixed = lowp != dmrgdev::P_F64;
+    const int max_refresh = 8;
     *nlo = 0;
     *n64 = 0;
     *conv = false;
-    // V0 = psi / |psi|
+    int refreshes = 0;
+    bool exact = true;        // every W column is an FP64 product
+    // V0 = psi / |psi|, W0 = H64 V0
     DEV(dmrgdev::dots(dev_, psi_.d(), 0, 1, psi_.d(), n, sc + 3));
     DEV(dmrgdev::copy_scaled_inv_norm(dev_, psi_.d(), n, sc + 3, Vm));
-    TRY(heff(B, Vm, Wm, in_low ? lowp : dmrgdev::P_F64));
-    (in_low ? *nlo : *n64) += 1;
+    TRY(heff(B, Vm, Wm, dmrgdev::P_F64));
+    *n64 += 1;
     int k = 1;
     DEV(dmrgdev::dots(dev_, Vm, n, 1, Wm, n, G));
     double theta = 0.0, rn = 0.0, prev_rn = 1e300;
     int stall = 0;
     const double tol = opt_.davidson_tol;
+    // reduced-precision residuals are trusted down to about rho times the last FP64 residual
+    const double rho = lowp == dmrgdev::P_BF16 ? 1e-2 : 1e-5;
+    double r_exact = 1e300;
     while (true) {
         DEV(dmrgdev::small_eigh(dev_, G, k, ldg, sc, s));
         DEV(dmrgdev::combine(dev_, Vm, n, k, s, 1.0, n, dv_x_.d(), 0));
@@ -1352,33 +1471,48 @@ dmrg_status Engine::davidson(Bond& B, double* theta_out, int64_t* nlo, int64_t* 
         DEV(dmrgdev::d2h(dev_, hs, sc, 2 * sizeof(double)));
         theta = hs[0];
         rn = std::sqrt(std::max(hs[1], 0.0));
-        int64_t nprod = *nlo + *n64;
-        if (in_low) {
-            // leave reduced precision when its residual passes tol or stops improving
-            bool stalled = rn > 0.5 * prev_rn;
-            stall = stalled ? stall + 1 : 0;
-            if (rn <= tol || stall >= 2 || nprod >= opt_.davidson_max_iter) {
-                in_low = false;
-                // restart from x with an FP64 product
+        const int64_t nprod = *nlo + *n64;
+#ifdef DMRG_TRACE
+        fprintf(stderr, "   dav k=%d exact=%d rn=%.3e theta=%.12f lo=%lld 64=%lld\n", k, (int)exact, rn, theta, (long long)*nlo, (long long)*n64);
+#endif
+        if (exact && rn <= tol) {
+            *conv = true;
+            break;
+        }
+        if (exact) r_exact = rn;
+        if (nprod >= opt_.davidson_max_iter) break;
+        if (mixed && !exact) {
+            stall = rn > 0.8 * prev_rn ? stall + 1 : 0;
+            prev_rn = rn;
+            if (rn <= std::max(tol, rho * r_exact) || stall >= 3) {
+                // FP64 refresh: V = [x], W = [H64 x]
                 DEV(dmrgdev::dots(dev_, dv_x_.d(), 0, 1, dv_x_.d(), n, sc + 3));
                 DEV(dmrgdev::copy_scaled_inv_norm(dev_, dv_x_.d(), n, sc + 3, Vm));
                 TRY(heff(B, Vm, Wm, dmrgdev::P_F64));
                 *n64 += 1;
                 k = 1;
                 DEV(dmrgdev::dots(dev_, Vm, n, 1, Wm, n, G));
+                exact = true;
+                stall = 0;
                 prev_rn = 1e300;
+                ++refreshes;
                 continue;
             }
-            prev_rn = rn;
-        } else if (rn <= tol) {
-            *conv = true;
-            break;
         }
-        if (nprod >= opt_.davidson_max_iter) break;
         DEV(dmrgdev::precond(dev_, dv_r_.d(), B.diag.d(), sc, n, dv_t_.d()));
         if (k >= kmax) {
             DEV(dmrgdev::dots(dev_, dv_x_.d(), 0, 1, dv_x_.d(), n, sc + 3));
             DEV(dmrgdev::copy_scaled_inv_norm(dev_, dv_x_.d(), n, sc + 3, Vm));
+            if (mixed && !exact) {
+                // restart as a refresh: the kept column becomes an FP64 product
+                TRY(heff(B, Vm, Wm, dmrgdev::P_F64));
+                *n64 += 1;
+                exact = true;
+                ++refreshes;
+                k = 1;
+                DEV(dmrgdev::dots(dev_, Vm, n, 1, Wm, n, G));
+                continue;
+            }
             DEV(dmrgdev::copy_scaled_inv_norm(dev_, dv_hx_.d(), n, sc + 3, Wm));
             k = 1;
             DEV(dmrgdev::dots(dev_, Vm, n, 1, Wm, n, G));
@@ -1393,7 +1527,7 @@ dmrg_status Engine::davidson(Bond& B, double* theta_out, int64_t* nlo, int64_t* 
         double tn2;
         DEV(dmrgdev::d2h(dev_, &tn2, sc + 2, sizeof(double)));
         if (std::sqrt(std::max(tn2, 0.0)) < 1e-12) {
-            if (in_low) {
+            if (mixed && !exact) {
                 stall = 2;
                 prev_rn = 0.0;
                 continue;
@@ -1401,11 +1535,14 @@ dmrg_status Engine::davidson(Bond& B, double* theta_out, int64_t* nlo, int64_t* 
             break;
         }
         DEV(dmrgdev::copy_scaled_inv_norm(dev_, dv_t_.d(), n, sc + 2, Vm + (size_t)k * n));
-        TRY(heff(B, Vm + (size_t)k * n, Wm + (size_t)k * n, in_low ? lowp : dmrgdev::P_F64));
-        (in_low ? *nlo : *n64) += 1;
-        // new column and row of G = V^T W
-        DEV(dmrgdev::dots(dev_, Vm, n, k + 1, Wm + (size_t)k * n, n, G + k, ldg));
-        DEV(dmrgdev::dots(dev_, Wm, n, k, Vm + (size_t)k * n, n, G + (size_t)k * ldg));
+        const bool low = mixed && refreshes < max_refresh;
+        TRY(heff(B, Vm + (size_t)k * n, Wm + (size_t)k * n, low ? lowp : dmrgdev::P_F64));
+        (low ? *nlo : *n64) += 1;
+        if (low) exact = false;
+        // new row of the projected matrix: G[k][a] = (H v_a)^T v_k, a <= k.  Coupling a
+        // new vector through the earlier vectors' products keeps the couplings to an
+        // FP64-refreshed x exact in the mixed modes; only the lower triangle is used.
+        DEV(dmrgdev::dots(dev_, Wm, n, k + 1, Vm + (size_t)k * n, n, G + (size_t)k * ldg));
         ++k;
     }
     // psi <- x normalised
@@ -1663,7 +1800,7 @@ dmrg_status Engine::density_matrix(Bond& B, bool left, double alpha, Buf& rho, s
     TRY(finish_plan(*this, g1, p1));
     TRY(finish_plan(*this, g2, p2));
     const OpSet& ops = left ? B.Sops : B.Eops;
-    void* bufs[4] = {psi_.p, ops.pool.p, phib.p, rho.p};
+    BufTable bufs{psi_.p, ops.pool.p, phib.p, rho.p};
     TRY(run_gemm(dmrgdev::P_F64, bufs, p1));
     TRY(run_gemm(dmrgdev::P_F64, bufs, p2));
     DEV(dmrgdev::sync(dev_));
@@ -1911,7 +2048,7 @@ dmrg_status Engine::truncate_and_move(int D, double alpha, double* disc) {
     GemmPlan p1, p2;
     TRY(finish_plan(*this, g1, p1));
     TRY(finish_plan(*this, g2, p2));
-    void* bufs[5] = {psi_.p, nw.iso.p, phib.p, npsi.p, far.iso.p};
+    BufTable bufs{psi_.p, nw.iso.p, phib.p, npsi.p, far.iso.p};
     TRY(run_gemm(dmrgdev::P_F64, bufs, p1));
     TRY(run_gemm(dmrgdev::P_F64, bufs, p2));
     // fall back to the hash-random start if the guess vanished
@@ -2036,7 +2173,7 @@ dmrg_status Engine::apply(const double* x, double* y, int prec) {
     if (!cur_) return fail(DMRG_ERR_STATE, "no current bond (run a sweep first)");
     if (!x || !y) return fail(DMRG_ERR_ARG, "null vector");
     if (prec < 0 || prec > 2) return fail(DMRG_ERR_ARG, "precision must be 0, 1 or 2");
-    return heff_launch(*cur_, x, y, prec);
+    return heff_launch(*cur_, x, y, prec, false);
 }
 
 dmrg_status Engine::energy(double* E) {

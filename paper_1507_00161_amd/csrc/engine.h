@@ -210,11 +210,15 @@ struct Term {
     int par;
 };
 
+using BufTable = std::array<void*, dmrgdev::kMaxBufs>;
+
 struct GemmPlan {
-    Buf tasks, chunks;
-    int ntasks = 0;
+    Buf tasks, chunks, reds;
+    int ntasks = 0, nreds = 0;
+    int64_t nslots = 0;     // split-K partial tiles
     int64_t nchunks = 0;
     double flops = 0.0;
+    double elems = 0.0;    // operand elements read + result elements written (algorithmic)
 };
 
 struct HeffGroup {
@@ -330,14 +334,17 @@ private:
     dmrg_status build_heff_plan(Bond& B);
     dmrg_status build_diag(Bond& B);
     dmrg_status heff(Bond& B, const double* x, double* y, int prec);
-    dmrg_status heff_launch(Bond& B, const double* x, double* y, int prec);
+    dmrg_status heff_launch(Bond& B, const double* x, double* y, int prec, bool timed);
+    void account(const HeffGroup& g, double es1, double es2);
     dmrg_status ensure_lo(Bond& B, int prec);
     dmrg_status davidson(Bond& B, double* theta, int64_t* nlo, int64_t* n64, bool* conv);
     dmrg_status truncate_and_move(int D, double alpha, double* disc);
     dmrg_status density_matrix(Bond& B, bool left, double alpha, Buf& rho,
                                std::vector<int64_t>& roff, std::vector<int>& rdim);
     dmrg_status random_psi(Bond& B, Buf& out);
-    dmrg_status run_gemm(int prec, void* const* bufs, const GemmPlan& p, int cprec = -1);
+    dmrg_status run_gemm(int prec, BufTable bufs, const GemmPlan& p, int cprec = -1);
+    dmrg_status ensure_partials(int64_t slots);
+    Buf partial_;
     dmrg_status ensure_dv(int64_t n, int kmax);
     std::vector<std::vector<double>> selection_iso(const std::vector<int>& dims, int D, int tag,
                                                    int pos, const std::vector<QN>& qs, bool mix,

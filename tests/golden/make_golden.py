@@ -1,0 +1,65 @@
+"""Write tests/golden/oracle_energies.json from the CPU oracle alone.
+
+Each case runs the oracle's two-site DMRG (oracle/dmrg.py) on a seeded
+workload with a fixed sweep schedule and options, and records the sweep
+energies.  The GPU parity tests run the library with the same workload,
+schedule, ordering and options and compare energies (relative 1e-8 in FP64,
+1e-6 in the mixed modes).  Nothing here touches the GPU library.
+
+    python tests/golden/make_golden.py
+"""
+from __future__ import annotations
+
+import json
+import os
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+
+from oracle import dmrg, ed  # noqa: E402
+from workloads import WORKLOADS, make_hamiltonian, make_space, random_ordering  # noqa: E402
+
+OPTS = dict(davidson_tol=1e-9, noise=1e-4, noise_sweeps=2, seed=7)
+
+CASES = [
+    # name, workload (or (space, seed, n_p, n_n, 2M)), ordering seed, D schedule
+    ("p_2p2n_D64", "p_2p2n", None, [64, 64]),
+    ("p_2p2n_M2_D16", ("p", 11, 2, 2, 4), None, [16, 16]),
+    ("sd_4p4n_D32", "sd_4p4n", None, [32, 32, 32]),
+    ("sd_3p2n_M1_rand_D24", ("sd", 13, 3, 2, 1), 5, [24, 24]),
+    ("pf_8p8n_D32", "pf_8p8n", None, [32, 32]),
+]
+
+
+def hamiltonian(spec):
+    if isinstance(spec, str):
+        return WORKLOADS[spec].hamiltonian()
+    space, seed, n_p, n_n, two_M = spec
+    return make_hamiltonian(make_space(space), seed, n_p, n_n, two_M)
+
+
+def main():
+    out = {"options": OPTS, "cases": {}}
+    for name, spec, oseed, sched in CASES:
+        h = hamiltonian(spec)
+        sp = h.space
+        order = None if oseed is None else random_ordering(sp.n_sites, oseed)
+        t = time.time()
+        o = dmrg.DMRG(h.eps, h.V, sp.species, sp.two_m, h.n_p, h.n_n, h.two_M, order,
+                      dmrg.Options(**OPTS))
+        energies = [o.sweep(D)["energy"] for D in sched]
+        case = {"workload": spec, "ordering_seed": oseed, "D": sched, "energies": energies,
+                "target": [h.n_p, h.n_n, h.two_M]}
+        if sp.n_sites <= 24:
+            case["exact"] = float(ed.ground_energy(h.eps, h.V, sp.species, sp.two_m,
+                                                   h.n_p, h.n_n, h.two_M)[0])
+        out["cases"][name] = case
+        print(f"{name}: {energies} ({time.time() - t:.1f} s)", flush=True)
+    with open(os.path.join(HERE, "oracle_energies.json"), "w") as f:
+        json.dump(out, f, indent=1)
+
+
+if __name__ == "__main__":
+    main()

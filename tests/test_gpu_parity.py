@@ -1,0 +1,190 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+* H_eff psi equals the Hamiltonian applied to determinants, element by
+  element, at every bond of full sweeps (determinant-selection mode, where
+  every block state is one determinant and the oracle's Slater-Condon rows
+  are the expected values), including the full 56Ni-sized pf 8p+8n space at
+  D = 2048 on sampled rows;
+* sweep energies equal the oracle's (tests/golden, written by the oracle
+  alone) to 1e-8 relative in FP64 and 1e-6 in the mixed modes;
+* exact diagonalisation and closed forms: p shell at exact D, the degenerate
+  pairing model at the pf 8p+8n size.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import ed
+from workloads import (WORKLOADS, make_hamiltonian, make_pairing, make_space, random_ordering)
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "oracle_energies.json")
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def pk():
+    import paper_1507_00161_amd as pk
+    pk.library()   # raises if the HIP library is missing: no fallback
+    return pk
+
+
+def _ctx(pk, h, **kw):
+    c = pk.Context(**kw)
+    sp = h.space
+    c.load_hamiltonian(sp.species, sp.two_m, h.eps, h.V.ravel(), h.n_p, h.n_n, h.two_M)
+    return c
+
+
+def _apply(c, x, torch_dev, prec=0):
+    import torch
+    xt = torch.tensor(x, device=torch_dev)
+    yt = torch.zeros_like(xt)
+    c.heff_apply(xt, yt, prec)
+    torch.cuda.synchronize()
+    return yt.cpu().numpy()
+
+
+def _chain(h, order):
+    return h.eps[order], h.V[np.ix_(order, order, order, order)]
+
+
+@pytest.mark.parametrize("space,n_p,n_n,two_M,D,rand", [
+    ("p", 2, 2, 0, 6, False),
+    ("sd", 2, 3, 1, 10, True),
+    ("pf", 3, 2, 1, 12, True),
+])
+def test_heff_equals_slater_condon_every_bond(pk, torch_dev, space, n_p, n_n, two_M, D, rand):
+    sp = make_space(space)
+    h = make_hamiltonian(sp, 31, n_p, n_n, two_M)
+    order = random_ordering(sp.n_sites, 2) if rand else np.arange(sp.n_sites)
+    eps_c, V_c = _chain(h, order)
+    c = _ctx(pk, h, davidson_tol=1e-9, select_basis=1, seed=99)
+    rng = np.random.default_rng(0)
+    nsteps = 2 * (sp.n_sites - 1)
+    worst = 0.0
+    for st in range(nsteps):
+        c.sweep_steps(D, 0 if st == 0 else 1, order)
+        bond, dim, qn, dims = c.heff_layout()
+        assert dims.prod(axis=1).sum() == dim
+        cfg = c.heff_configs()
+        assert len(set(cfg.tolist())) == dim
+        x = rng.normal(size=dim)
+        y = _apply(c, x, torch_dev)
+        rows = np.arange(dim) if dim <= 300 else rng.choice(dim, 300, replace=False)
+        ref = ed.apply_rows(eps_c, V_c, cfg, x, rows)
+        worst = max(worst, np.abs(y[rows] - ref).max() / max(1.0, np.abs(ref).max()))
+    assert worst < 1e-12
+
+
+def test_heff_full_size_pf_8p8n_D2048_sampled_rows(pk, torch_dev):
+    """The 56Ni-sized space at the benchmark's bond dimension and precisions:
+    sampled output rows of H_eff psi against Slater-Condon rows."""
+    h = WORKLOADS["pf_8p8n"].hamiltonian()
+    c = _ctx(pk, h, davidson_tol=1e-6, select_basis=1, seed=3)
+    c.sweep_steps(2048, 19)          # to the middle of the chain
+    bond, dim, qn, dims = c.heff_layout()
+    assert bond == 19 and dim > 10000
+    cfg = c.heff_configs()
+    rng = np.random.default_rng(1)
+    x = rng.normal(size=dim)
+    rows = rng.choice(dim, 120, replace=False)
+    ref = ed.apply_rows(h.eps, h.V, cfg, x, rows)
+    y64 = _apply(c, x, torch_dev, 0)
+    assert np.abs(y64[rows] - ref).max() < 1e-11 * max(1.0, np.abs(ref).max())
+    y32 = _apply(c, x, torch_dev, 1)
+    assert np.linalg.norm(y32 - y64) < 1e-5 * np.linalg.norm(y64)
+    y16 = _apply(c, x, torch_dev, 2)
+    assert np.linalg.norm(y16 - y64) < 2e-2 * np.linalg.norm(y64)
+
+
+def test_heff_is_symmetric_and_linear(pk, torch_dev):
+    h = WORKLOADS["sd_4p4n"].hamiltonian()
+    c = _ctx(pk, h, davidson_tol=1e-8, noise=1e-4, noise_sweeps=1, seed=2)
+    c.sweep(24)
+    c.sweep_steps(24, 11)
+    bond, dim, _, _ = c.heff_layout()
+    rng = np.random.default_rng(3)
+    x1, x2 = rng.normal(size=dim), rng.normal(size=dim)
+    y1, y2 = _apply(c, x1, torch_dev), _apply(c, x2, torch_dev)
+    assert abs(x2 @ y1 - x1 @ y2) < 1e-11 * abs(x2 @ y1) + 1e-11
+    y12 = _apply(c, 2.0 * x1 - 3.0 * x2, torch_dev)
+    assert np.abs(y12 - (2 * y1 - 3 * y2)).max() < 1e-11 * np.abs(y12).max()
+
+
+def _golden():
+    with open(GOLDEN) as f:
+        return json.load(f)
+
+
+def _golden_ham(spec):
+    if isinstance(spec, str):
+        return WORKLOADS[spec].hamiltonian()
+    space, seed, n_p, n_n, two_M = spec
+    return make_hamiltonian(make_space(space), seed, n_p, n_n, two_M)
+
+
+@pytest.mark.parametrize("name", ["p_2p2n_D64", "p_2p2n_M2_D16", "sd_4p4n_D32", "sd_3p2n_M1_rand_D24",
+                                  "pf_8p8n_D32"])
+@pytest.mark.parametrize("precision,rtol", [(0, 1e-8), (1, 1e-6), (2, 1e-6)])
+def test_sweep_energies_match_oracle(pk, name, precision, rtol):
+    g = _golden()
+    case = g["cases"][name]
+    h = _golden_ham(case["workload"])
+    sp = h.space
+    order = None if case["ordering_seed"] is None else random_ordering(sp.n_sites, case["ordering_seed"])
+    c = _ctx(pk, h, precision=precision, **g["options"])
+    for D, e_ref in zip(case["D"], case["energies"]):
+        r = c.sweep(D, order)
+        assert r["code"] == 0
+        assert abs(r["energy"] - e_ref) <= rtol * abs(e_ref), (D, r["energy"], e_ref)
+        if "exact" in case:
+            assert r["energy"] >= case["exact"] - 1e-9        # variational bound
+    assert c.energy() == r["energy"]
+
+
+def test_p_shell_exact_bond_dimension_equals_ed(pk):
+    h = WORKLOADS["p_2p2n"].hamiltonian()
+    e0 = ed.ground_energy(h.eps, h.V, h.space.species, h.space.two_m, 2, 2, 0)[0]
+    for order in (None, random_ordering(12, 4)):
+        c = _ctx(pk, h, davidson_tol=1e-10, noise=1e-4, noise_sweeps=1)
+        for _ in range(2):
+            r = c.sweep(64, order)
+        assert abs(r["energy"] - e0) < 1e-10
+
+
+def test_pairing_closed_form_pf_8p8n(pk):
+    """Degenerate pairing in the 56Ni-sized space (pf, 8p + 8n):
+    E = 16 eps - G [4 (10 - 4 + 1) * 2] = 16 eps - 56 G.  The state has large
+    exactly degenerate density-matrix multiplets (dropped whole at the cut),
+    so it needs D = 1024 here; smaller D stays in a trapped state."""
+    sp = make_space("pf")
+    G, eps0 = 0.35, -1.25
+    h = make_pairing(sp, G, eps0, 8, 8)
+    c = _ctx(pk, h, davidson_tol=1e-9, noise=1e-4, noise_sweeps=2, seed=5)
+    for _ in range(2):
+        r = c.sweep(1024)
+    assert abs(r["energy"] - (16 * eps0 - 56 * G)) < 1e-8
+
+
+def test_sweep_many_matches_single_contexts(pk):
+    hs = [WORKLOADS["p_2p2n"].hamiltonian(), make_hamiltonian(make_space("sd"), 5, 2, 2, 0)]
+    single = []
+    for h in hs:
+        c = _ctx(pk, h, davidson_tol=1e-9, seed=3)
+        single.append(c.sweep(16)["energy"])
+    ctxs = [_ctx(pk, h, davidson_tol=1e-9, seed=3) for h in hs]
+    st, out = pk.sweep_many(ctxs, [16, 16])
+    assert st == 0
+    for o, e in zip(out, single):
+        assert o["status"] == 0 and abs(o["energy"] - e) < 1e-10 * abs(e)
