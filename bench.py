@@ -66,7 +66,11 @@ def run_schedule(workload, prec: str, warmup: int, steps: int, D_main: int, seed
                 tot[key] = tot.get(key, 0) + v
         log(f"[{prec}] timed sweep {k} D={D_main}: E={r['energy']:.9f} {walls[-1]:.2f}s "
             f"products lo/64={r['products_low']}/{r['products_fp64']} "
-            f"heff {r['heff_flops'] / max(r['heff_seconds'], 1e-12) / 1e12:.2f} TF/s")
+            f"heff {r['heff_flops'] / max(r['heff_seconds'], 1e-12) / 1e12:.2f} TF/s; "
+            f"time in products {r['heff_seconds']:.2f}s, truncation+renorm+prediction "
+            f"{r['renorm_seconds']:.2f}s (density {r['density_seconds']:.2f}, eig {r['eig_seconds']:.2f}, "
+            f"renormalize {r['renormalize_seconds']:.2f}, predict {r['predict_seconds']:.2f}), "
+            f"blocking+plans {r['blocking_seconds']:.2f}s")
     ctx.close()
     return dict(energy=energy, walls=walls, tot=tot)
 

@@ -75,6 +75,10 @@ typedef struct dmrg_sweep_stats {
     double sweep_seconds;     /* wall time of the sweep */
     double renorm_seconds;    /* wall time in truncation + renormalisation + prediction */
     double blocking_seconds;  /* wall time building enlarged-block operators and plans */
+    double density_seconds;   /* of renorm_seconds: reduced density matrices */
+    double eig_seconds;       /* of renorm_seconds: sector eigendecompositions + selection */
+    double renormalize_seconds; /* of renorm_seconds: U^T O U of the kept operators */
+    double predict_seconds;   /* of renorm_seconds: next-bond guess */
     int32_t status;           /* per-context status (dmrg_sweep_many) */
     int32_t steps;            /* two-site steps done */
     /* per-kernel accounting of the H_eff.psi grouped GEMMs (HIP events on the

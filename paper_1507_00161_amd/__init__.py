@@ -40,7 +40,9 @@ class SweepStats(ctypes.Structure):
                 ("solves", ctypes.c_int64), ("not_converged", ctypes.c_int64),
                 ("heff_flops", ctypes.c_double), ("heff_seconds", ctypes.c_double),
                 ("sweep_seconds", ctypes.c_double), ("renorm_seconds", ctypes.c_double),
-                ("blocking_seconds", ctypes.c_double), ("status", ctypes.c_int32),
+                ("blocking_seconds", ctypes.c_double), ("density_seconds", ctypes.c_double),
+                ("eig_seconds", ctypes.c_double), ("renormalize_seconds", ctypes.c_double),
+                ("predict_seconds", ctypes.c_double), ("status", ctypes.c_int32),
                 ("steps", ctypes.c_int32),
                 ("gemm1_launches", ctypes.c_int64), ("gemm2_launches", ctypes.c_int64),
                 ("gemm1_seconds", ctypes.c_double), ("gemm2_seconds", ctypes.c_double),

@@ -65,10 +65,17 @@ constexpr int kTileN = 64;
 
 enum Prec { P_F64 = 0, P_F32 = 1, P_BF16 = 2 };
 
-// A and B of one launch share a precision (ab_prec); C is c_prec.  Supported:
-// (F64, F64), (F32, F32), (BF16, F32), (BF16, BF16).  Accumulation is FP64
-// for F64 operands and FP32 otherwise.
-int gemm(Ctx* c, int ab_prec, int c_prec, void* const* bufs, const GemmTask* d_tasks, int ntasks,
+// Schedule of a persistent launch of `nwg` work-groups: work-group w runs
+// tasks [wg_off[w], wg_off[w+1]) in order (wg_off is a device array of nwg + 1
+// entries; work-group w lives on XCD w % 8); tasks [nfull, ntasks) have no
+// chunks and only clear their tile.  A and B of one launch share a precision
+// (ab_prec); C is c_prec.  Supported: (F64, F64), (F32, F32), (BF16, F32),
+// (BF16, BF16).  Accumulation is FP64 for F64 operands and FP32 otherwise.
+struct Sched {
+    const int32_t* wg_off;
+    int32_t nwg, nfull, ntasks;
+};
+int gemm(Ctx* c, int ab_prec, int c_prec, void* const* bufs, const GemmTask* d_tasks, const Sched& sched,
          const GemmChunk* d_chunks);
 int gemm_reduce(Ctx* c, int c_prec, void* const* bufs, const RedTask* d_tasks, int ntasks);
 
@@ -133,8 +140,15 @@ int convert(Ctx* c, int from_prec, const void* src, int to_prec, void* dst, int6
 // A (n x n, symmetric) is overwritten with eigenvectors: row e of the
 // row-major array is the eigenvector of w[e]; w ascending.
 int syevd(Ctx* c, int n, double* A, double* w);
-// U[r, col] = s_col * E[idx[col], r] (E rows = eigenvectors of length n),
-// s_col = +-1 making the first largest-magnitude entry positive.
-int gather_evecs(Ctx* c, const double* E, int n, const int32_t* d_idx, int k, double* U);
+// `count` symmetric P x P matrices at stride P*P, solved together (same
+// output convention; w at stride P).
+int syevd_batched(Ctx* c, int P, int count, double* A, double* w);
+// Prepare padded slots: for slot s (base + s*P*P, real size n[s]) write 0
+// outside the leading n x n block and -1 on the padding diagonal, so the
+// padding eigenpairs are (-1, unit vectors of the padding rows).
+int pad_init(Ctx* c, double* base, int P, int count, const int32_t* d_n);
+// U[r, col] = s_col * E[idx[col] * stride + r] for r < n (E rows = eigenvectors),
+// s_col = +-1 making the first largest-magnitude entry (r < n) positive.
+int gather_evecs(Ctx* c, const double* E, int n, int stride, const int32_t* d_idx, int k, double* U);
 
 }  // namespace dmrgdev

@@ -12,6 +12,7 @@
 #include <rocblas/rocblas.h>
 #include <rocsolver/rocsolver.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -35,6 +36,7 @@ struct Ctx {
     double* syev_e = nullptr;
     size_t syev_cap = 0;
     int* info = nullptr;
+    size_t info_cap = 0;
 };
 
 static int seterr(Ctx* c, const char* what, hipError_t e) {
@@ -86,6 +88,7 @@ int ctx_create(int device, void* stream, Ctx** out, char* err, size_t errlen) {
         delete c;
         return fail("hipMalloc failed");
     }
+    c->info_cap = 1;
     *out = c;
     return 0;
 }
@@ -209,151 +212,238 @@ template <> struct MmaTraits<float> {
     static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane >> 4) + r; }
 };
 
-// Register staging of one K slice (E = BK*64/256 elements per thread).
-// Two access patterns: "along K" (the operand is stored with K contiguous:
-// A non-transposed, B transposed) and "along M/N" (A transposed, B plain).
+// Register staging of one K slice for a 64-row operand tile (E = BK/4
+// elements per thread).  LDS holds the tile as S[r][k] (k contiguous) with
+// row stride LDK = BK + 4 floats (BK + 2 doubles): the MFMA fragment reads
+// (16 rows x 4 consecutive k per wave) then hit distinct banks.  Global
+// loads are coalesced along whichever dimension is contiguous in memory:
+// "along K" (A plain, B transposed) or "along M/N" (A transposed, B plain).
 template <class T, int BK>
 struct Slice {
-    static constexpr int E = BK * 64 / NTH;
+    static constexpr int E = BK / 4;
+    static constexpr int LDK = BK + (sizeof(T) == 8 ? 2 : 4);
     T v[E];
-    // operand stored row-major with K contiguous: element (r, k) at P[r*ld + k]
+    uint32_t ok;   // bit u: element u lies inside the operand
+    T scale;
+    // Loads are issued unconditionally (an element outside the operand reads
+    // its first element instead) so that all of them are in flight at once;
+    // masking and scaling happen at the LDS store, after the MFMAs of the
+    // current slice.
+    // element (r, k) at P[r*ld + k]: lane -> k = t % BK, rows t / BK + (256 / BK) u
     __device__ __forceinline__ void load_k(const T* __restrict__ P, int ld, int r0, int rmax, int k0, int K,
-                                           T scale, int tid) {
-        const int r = tid >> 2, kk = (tid & 3) * E;
-        const T* src = P + (int64_t)(r0 + r) * ld + k0 + kk;
+                                           T s, int tid) {
+        constexpr int RS = NTH / BK;
+        const int k = tid % BK, r = tid / BK;
+        const bool kin = k0 + k < K;
+        scale = s;
+        ok = 0;
 #pragma unroll
-        for (int u = 0; u < E; ++u) v[u] = (r < rmax && k0 + kk + u < K) ? src[u] * scale : T(0);
+        for (int u = 0; u < E; ++u) {
+            const int rr = r + RS * u;
+            const bool in = kin && rr < rmax;
+            v[u] = P[in ? (int64_t)(r0 + rr) * ld + k0 + k : 0];
+            ok |= (uint32_t)in << u;
+        }
     }
-    // operand stored row-major with M (or N) contiguous: element (r, k) at P[k*ld + r]
+    // element (r, k) at P[k*ld + r]: lane -> r = t % 64, k = t / 64 + 4 u
     __device__ __forceinline__ void load_m(const T* __restrict__ P, int ld, int r0, int rmax, int k0, int K,
-                                           T scale, int tid) {
-        constexpr int TPR = 64 / E;   // threads per k row
-        const int kk = tid / TPR, r = (tid % TPR) * E;
-        const T* src = P + (int64_t)(k0 + kk) * ld + r0 + r;
+                                           T s, int tid) {
+        const int r = tid & 63, k = tid >> 6;
+        const bool rin = r < rmax;
+        scale = s;
+        ok = 0;
 #pragma unroll
-        for (int u = 0; u < E; ++u) v[u] = (r + u < rmax && k0 + kk < K) ? src[u] * scale : T(0);
+        for (int u = 0; u < E; ++u) {
+            const int kk = k + 4 * u;
+            const bool in = rin && k0 + kk < K;
+            v[u] = P[in ? (int64_t)(k0 + kk) * ld + r0 + r : 0];
+            ok |= (uint32_t)in << u;
+        }
     }
-    // LDS tile S[k][r] with row stride LD
-    template <int LD>
+    __device__ __forceinline__ T get(int u) const { return ((ok >> u) & 1u) ? v[u] * scale : T(0); }
     __device__ __forceinline__ void store_k(T* __restrict__ S, int tid) const {
-        const int r = tid >> 2, kk = (tid & 3) * E;
+        constexpr int RS = NTH / BK;
+        const int k = tid % BK, r = tid / BK;
 #pragma unroll
-        for (int u = 0; u < E; ++u) S[(kk + u) * LD + r] = v[u];
+        for (int u = 0; u < E; ++u) S[(r + RS * u) * LDK + k] = get(u);
     }
-    template <int LD>
     __device__ __forceinline__ void store_m(T* __restrict__ S, int tid) const {
-        constexpr int TPR = 64 / E;
-        const int kk = tid / TPR, r = (tid % TPR) * E;
+        const int r = tid & 63, k = tid >> 6;
 #pragma unroll
-        for (int u = 0; u < E; ++u) S[kk * LD + r + u] = v[u];
+        for (int u = 0; u < E; ++u) S[r * LDK + k + 4 * u] = get(u);
     }
 };
 
-// Work-groups are dispatched round-robin over the 8 XCDs; map consecutive
-// tasks (tiles of one output block, which share operands) to one XCD so
-// that they meet in the same L2.  The grid is padded to a multiple of 8.
+// Work-groups are dispatched round-robin over the 8 XCDs: work-group b runs
+// on XCD b % 8.  A launch gives each XCD its own task range (the host deals
+// output blocks to XCDs so that the tiles of one block share an L2).
 __device__ __forceinline__ int xcd_task(int ntasks) {
     const int per = (ntasks + 7) >> 3;
     const int b = blockIdx.x;
     return (b & 7) * per + (b >> 3);
 }
 
+// Persistent grouped GEMM.  Work-group w runs its task list
+// [wg_off[w], wg_off[w+1]) (balanced on the host).  One software pipeline runs
+// over the K slices of all its chunks and tasks: the next slice's global loads
+// (possibly of the next task) are in flight while the MFMAs consume the current
+// slice from LDS; a task's epilogue is written when its last slice has been
+// consumed.
 template <class T, class TC, int BK>
-__global__ void __launch_bounds__(NTH) k_gemm(Bufs bufs, const GemmTask* __restrict__ tasks,
-                                              const GemmChunk* __restrict__ chunks, int ntasks) {
+__global__ void __launch_bounds__(NTH, 4) k_gemm(Bufs bufs, const GemmTask* __restrict__ tasks,
+                                              const GemmChunk* __restrict__ chunks, Sched sc) {
     typedef typename MmaTraits<T>::acc_t acc_t;
-    constexpr int LDA = TM + 16, LDB = TN + 16;   // padding: lane groups hit distinct LDS banks
-    __shared__ T As[2][BK * LDA];
-    __shared__ T Bs[2][BK * LDB];
-    const int ti = xcd_task(ntasks);
-    if (ti >= ntasks) return;
-    const GemmTask tk = tasks[ti];
+    typedef Slice<T, BK> SL;
+    constexpr int LDK = SL::LDK;
+    __shared__ T As[2][TM * LDK];
+    __shared__ T Bs[2][TN * LDK];
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63;
     const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;   // wave quadrant
+    const int fr = lane & 15, fk = lane >> 4;
+    int ti = sc.wg_off[blockIdx.x];
+    const int hi = sc.wg_off[blockIdx.x + 1];
     acc_t acc[2][2];
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b) acc[a][b] = acc_t{0, 0, 0, 0};
-    Slice<T, BK> ra, rb;
-    auto load = [&](const GemmChunk& ch, int k0) {
+    SL ra, rb;
+    auto load = [&](const GemmTask& t, const GemmChunk& ch, int k0) {
         const T* A = (const T*)bufs.p[ch.a_buf] + ch.a_off;
         const T* B = (const T*)bufs.p[ch.b_buf] + ch.b_off;
         const T alpha = (T)ch.alpha;
-        if (!ch.a_trans) ra.load_k(A, ch.lda, tk.m0, tk.mt, k0, ch.K, alpha, tid);
-        else ra.load_m(A, ch.lda, tk.m0, tk.mt, k0, ch.K, alpha, tid);
-        if (!ch.b_trans) rb.load_m(B, ch.ldb, tk.n0, tk.nt, k0, ch.K, T(1), tid);
-        else rb.load_k(B, ch.ldb, tk.n0, tk.nt, k0, ch.K, T(1), tid);
+        if (!ch.a_trans) ra.load_k(A, ch.lda, t.m0, t.mt, k0, ch.K, alpha, tid);
+        else ra.load_m(A, ch.lda, t.m0, t.mt, k0, ch.K, alpha, tid);
+        if (!ch.b_trans) rb.load_m(B, ch.ldb, t.n0, t.nt, k0, ch.K, T(1), tid);
+        else rb.load_k(B, ch.ldb, t.n0, t.nt, k0, ch.K, T(1), tid);
     };
     auto store = [&](const GemmChunk& ch, int buf) {
-        if (!ch.a_trans) ra.template store_k<LDA>(As[buf], tid);
-        else ra.template store_m<LDA>(As[buf], tid);
-        if (!ch.b_trans) rb.template store_m<LDB>(Bs[buf], tid);
-        else rb.template store_k<LDB>(Bs[buf], tid);
+        if (!ch.a_trans) ra.store_k(As[buf], tid);
+        else ra.store_m(As[buf], tid);
+        if (!ch.b_trans) rb.store_m(Bs[buf], tid);
+        else rb.store_k(Bs[buf], tid);
     };
-    int c = tk.chunk_begin;
-    if (c < tk.chunk_end) {
+    auto epilogue = [&](const GemmTask& t) {
+        TC* C = (TC*)bufs.p[t.c_buf] + t.c_off;
+        const int64_t ldc = t.c_local ? TN : t.ldc;
+        const int64_t base = t.c_local ? 0 : (int64_t)t.m0 * t.ldc + t.n0;
+        TC old[2][2][4];
+        if (t.beta) {   // all reads in flight before the first use
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < 2; ++b)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int row = wm + a * 16 + MmaTraits<T>::row(lane, r);
+                        const int col = wn + b * 16 + (lane & 15);
+                        const bool in = row < t.mt && col < t.nt;
+                        old[a][b][r] = C[in ? base + (int64_t)row * ldc + col : base];
+                    }
+        }
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int row = wm + a * 16 + MmaTraits<T>::row(lane, r);
+                    const int col = wn + b * 16 + (lane & 15);
+                    if (row < t.mt && col < t.nt) {
+                        double v = (double)acc[a][b][r];
+                        if (t.beta) v += (double)old[a][b][r];
+                        C[base + (int64_t)row * ldc + col] = (TC)v;
+                    }
+                    acc[a][b][r] = 0;
+                }
+    };
+    if (ti < hi) {
+        GemmTask tk = tasks[ti];
+        int c = tk.chunk_begin;
         GemmChunk ch = chunks[c];
         int k0 = 0;
-        load(ch, k0);
+        // descriptors of this work-group's next task, fetched a whole task ahead
+        int pti = ti + 1;
+        GemmTask ptk = tk;
+        GemmChunk pch = ch;
+        if (pti < hi) {
+            ptk = tasks[pti];
+            pch = chunks[ptk.chunk_begin];
+        }
+        load(tk, ch, 0);
         store(ch, 0);
         __syncthreads();
         int buf = 0;
         while (true) {
-            // next slice: same chunk or the next one
+            // successor slice: same chunk, next chunk, or the next task's first chunk
+            GemmTask ntk = tk;
             int nc = c, nk0 = k0 + BK;
             GemmChunk nch = ch;
+            bool newtask = false, more = true;
             if (nk0 >= ch.K) {
-                nc = c + 1;
                 nk0 = 0;
-                if (nc < tk.chunk_end) nch = chunks[nc];
+                nc = c + 1;
+                if (nc < tk.chunk_end) {
+                    nch = chunks[nc];
+                } else {
+                    newtask = true;
+                    more = pti < hi;
+                    ntk = ptk;
+                    nc = ptk.chunk_begin;
+                    nch = pch;
+                }
             }
-            const bool more = nc < tk.chunk_end;
-            if (more) load(nch, nk0);   // global loads in flight during the MFMAs
+            if (more) load(ntk, nch, nk0);   // global loads in flight during the MFMAs
             const T* Ab = As[buf];
             const T* Bb = Bs[buf];
+            T av[BK / 4][2], bv[BK / 4][2];
 #pragma unroll
-            for (int ks = 0; ks < BK; ks += 4) {
-                const int kr = ks + (lane >> 4);
-                T av[2], bv[2];
+            for (int s4 = 0; s4 < BK / 4; ++s4) {
 #pragma unroll
-                for (int a = 0; a < 2; ++a) av[a] = Ab[kr * LDA + wm + a * 16 + (lane & 15)];
+                for (int a = 0; a < 2; ++a) av[s4][a] = Ab[(wm + a * 16 + fr) * LDK + 4 * s4 + fk];
 #pragma unroll
-                for (int b = 0; b < 2; ++b) bv[b] = Bb[kr * LDB + wn + b * 16 + (lane & 15)];
+                for (int b = 0; b < 2; ++b) bv[s4][b] = Bb[(wn + b * 16 + fr) * LDK + 4 * s4 + fk];
+            }
+#pragma unroll
+            for (int s4 = 0; s4 < BK / 4; ++s4)
 #pragma unroll
                 for (int a = 0; a < 2; ++a)
 #pragma unroll
-                    for (int b = 0; b < 2; ++b) acc[a][b] = MmaTraits<T>::mma(av[a], bv[b], acc[a][b]);
+                    for (int b = 0; b < 2; ++b) acc[a][b] = MmaTraits<T>::mma(av[s4][a], bv[s4][b], acc[a][b]);
+            if (newtask) {
+                epilogue(tk);
+                if (more) {
+                    ti = pti;
+                    pti = ti + 1;
+                    if (pti < hi) {
+                        ptk = tasks[pti];
+                        pch = chunks[ptk.chunk_begin];
+                    }
+                }
             }
             if (more) store(nch, buf ^ 1);
             __syncthreads();
             if (!more) break;
+            tk = ntk;
             c = nc;
             k0 = nk0;
             ch = nch;
             buf ^= 1;
         }
     }
-    // epilogue
-    TC* C = (TC*)bufs.p[tk.c_buf] + tk.c_off;
-    const int64_t ldc = tk.c_local ? TN : tk.ldc;
-    const int64_t base = tk.c_local ? 0 : (int64_t)tk.m0 * tk.ldc + tk.n0;
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int b = 0; b < 2; ++b)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                int row = wm + a * 16 + MmaTraits<T>::row(lane, r);
-                int col = wn + b * 16 + (lane & 15);
-                if (row < tk.mt && col < tk.nt) {
-                    TC* dst = C + base + (int64_t)row * ldc + col;
-                    double v = (double)acc[a][b][r];
-                    if (tk.beta) v += (double)*dst;
-                    *dst = (TC)v;
-                }
-            }
+    // tasks without chunks: clear their tile (beta = 0) or leave it (beta = 1)
+    for (int t = sc.nfull + blockIdx.x; t < sc.ntasks; t += gridDim.x) {
+        const GemmTask z = tasks[t];
+        if (z.beta) continue;
+        TC* C = (TC*)bufs.p[z.c_buf] + z.c_off;
+        const int64_t ldc = z.c_local ? TN : z.ldc;
+        const int64_t base = z.c_local ? 0 : (int64_t)z.m0 * z.ldc + z.n0;
+        for (int e = tid; e < TM * TN; e += NTH) {
+            const int r = e / TN, q = e % TN;
+            if (r < z.mt && q < z.nt) C[base + (int64_t)r * ldc + q] = (TC)0;
+        }
+    }
 }
 
 // ---- BF16: K slice 32, one v_mfma_f32_16x16x32_bf16 per 16x16 block and slice
@@ -416,6 +506,7 @@ __global__ void __launch_bounds__(NTH) k_gemm_bf16(Bufs bufs, const GemmTask* __
     const int ti = xcd_task(ntasks);
     if (ti >= ntasks) return;
     const GemmTask tk = tasks[ti];
+    if (tk.chunk_begin == tk.chunk_end && tk.beta) return;
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63;
     const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
@@ -475,15 +566,17 @@ __global__ void __launch_bounds__(NTH) k_gemm_bf16(Bufs bufs, const GemmTask* __
             }
 }
 
-int gemm(Ctx* c, int ab, int cp, void* const* bufs, const GemmTask* tasks, int ntasks, const GemmChunk* chunks) {
+int gemm(Ctx* c, int ab, int cp, void* const* bufs, const GemmTask* tasks, const Sched& sc,
+         const GemmChunk* chunks) {
+    const int ntasks = sc.ntasks;
     if (ntasks <= 0) return 0;
     Bufs b;
     for (int i = 0; i < kMaxBufs; ++i) b.p[i] = bufs[i];
-    dim3 grid(((ntasks + 7) / 8) * 8), block(NTH);
+    dim3 pgrid(std::max(1, sc.nwg)), block(NTH), grid(((ntasks + 7) / 8) * 8);
     if (ab == P_F64 && cp == P_F64)
-        hipLaunchKernelGGL((k_gemm<double, double, 16>), grid, block, 0, c->stream, b, tasks, chunks, ntasks);
+        hipLaunchKernelGGL((k_gemm<double, double, 16>), pgrid, block, 0, c->stream, b, tasks, chunks, sc);
     else if (ab == P_F32 && cp == P_F32)
-        hipLaunchKernelGGL((k_gemm<float, float, 32>), grid, block, 0, c->stream, b, tasks, chunks, ntasks);
+        hipLaunchKernelGGL((k_gemm<float, float, 32>), pgrid, block, 0, c->stream, b, tasks, chunks, sc);
     else if (ab == P_BF16 && cp == P_F32)
         hipLaunchKernelGGL((k_gemm_bf16<float>), grid, block, 0, c->stream, b, tasks, chunks, ntasks);
     else if (ab == P_BF16 && cp == P_BF16)
@@ -743,14 +836,16 @@ int copy_scaled_inv_norm(Ctx* c, const double* x, int64_t n, const double* n2, d
 }
 
 // Lowest eigenpair of a k x k symmetric matrix (k <= 32): one wave, cyclic
-// Jacobi with the round-robin pair schedule (k/2 disjoint rotations per round).
+// Jacobi with the round-robin pair schedule (k/2 disjoint rotations per
+// round; in round r position i holds index 0 for i = 0, else
+// 1 + (i - 1 + r) mod (kk - 1)).  Stops when the off-diagonal norm is below
+// 1e-14 of the matrix norm (eigenvalue error ~ its square).
 __global__ void __launch_bounds__(64) k_small_eigh(const double* __restrict__ G, int k, int ldg,
                                                    double* __restrict__ theta, double* __restrict__ s) {
     __shared__ double A[32][33];
     __shared__ double Vm[32][33];
     __shared__ double cs[16][2];
     __shared__ int pr[16][2];
-    __shared__ int order[32];
     __shared__ double red[64];
     const int t = threadIdx.x;
     const int kk = (k + 1) & ~1;   // even size; a padded index is never rotated
@@ -761,10 +856,8 @@ __global__ void __launch_bounds__(64) k_small_eigh(const double* __restrict__ G,
         A[i][j] = v;
         Vm[i][j] = i == j ? 1.0 : 0.0;
     }
-    if (t < 32) order[t] = t;
     __syncthreads();
-    for (int sweep = 0; sweep < 40; ++sweep) {
-        // convergence: off-diagonal norm vs total norm
+    for (int sweep = 0; sweep < 30 && kk > 1; ++sweep) {
         double off = 0.0, tot = 0.0;
         for (int e = t; e < k * k; e += 64) {
             int i = e / k, j = e % k;
@@ -772,26 +865,16 @@ __global__ void __launch_bounds__(64) k_small_eigh(const double* __restrict__ G,
             tot += v;
             if (i != j) off += v;
         }
-        red[t] = off;
-        __syncthreads();
         for (int o = 32; o > 0; o >>= 1) {
-            if (t < o) red[t] += red[t + o];
-            __syncthreads();
+            off += __shfl_xor(off, o, 64);
+            tot += __shfl_xor(tot, o, 64);
         }
-        double offs = red[0];
-        __syncthreads();
-        red[t] = tot;
-        __syncthreads();
-        for (int o = 32; o > 0; o >>= 1) {
-            if (t < o) red[t] += red[t + o];
-            __syncthreads();
-        }
-        double tots = red[0];
-        __syncthreads();
-        if (offs <= 1e-32 * tots || offs < 1e-300) break;
+        if (off <= 1e-28 * tot || off < 1e-300) break;
         for (int round = 0; round < kk - 1; ++round) {
             if (t < kk / 2) {
-                int p = order[t], q = order[kk - 1 - t];
+                const int i1 = t, i2 = kk - 1 - t;
+                int p = i1 == 0 ? 0 : 1 + (i1 - 1 + round) % (kk - 1);
+                int q = 1 + (i2 - 1 + round) % (kk - 1);
                 if (p > q) {
                     int x = p;
                     p = q;
@@ -813,7 +896,6 @@ __global__ void __launch_bounds__(64) k_small_eigh(const double* __restrict__ G,
                 cs[t][1] = sn;
             }
             __syncthreads();
-            // columns: A[:, p], A[:, q] and V
             for (int e = t; e < (kk / 2) * k; e += 64) {
                 int pi = e / k, i = e % k;
                 int p = pr[pi][0], q = pr[pi][1];
@@ -827,7 +909,6 @@ __global__ void __launch_bounds__(64) k_small_eigh(const double* __restrict__ G,
                 Vm[i][q] = sn * vip + c * viq;
             }
             __syncthreads();
-            // rows: A[p, :], A[q, :]
             for (int e = t; e < (kk / 2) * k; e += 64) {
                 int pi = e / k, j = e % k;
                 int p = pr[pi][0], q = pr[pi][1];
@@ -836,13 +917,6 @@ __global__ void __launch_bounds__(64) k_small_eigh(const double* __restrict__ G,
                 double apj = A[p][j], aqj = A[q][j];
                 A[p][j] = c * apj - sn * aqj;
                 A[q][j] = sn * apj + c * aqj;
-            }
-            __syncthreads();
-            // rotate the round-robin order (index 0 fixed)
-            if (t == 0) {
-                int last = order[kk - 1];
-                for (int x = kk - 1; x > 1; --x) order[x] = order[x - 1];
-                order[1] = last;
             }
             __syncthreads();
         }
@@ -918,14 +992,60 @@ int syevd(Ctx* c, int n, double* A, double* w) {
     return 0;
 }
 
+int syevd_batched(Ctx* c, int P, int count, double* A, double* w) {
+    if (count <= 0 || P <= 0) return 0;
+    size_t need = (size_t)P * count;
+    if (c->syev_cap < need) {
+        if (c->syev_e) hipFree(c->syev_e);
+        c->syev_e = nullptr;
+        c->syev_cap = 0;
+        HIPCHK(c, hipMalloc(&c->syev_e, need * sizeof(double)));
+        c->syev_cap = need;
+    }
+    if (c->info_cap < (size_t)count) {
+        if (c->info) hipFree(c->info);
+        c->info = nullptr;
+        c->info_cap = 0;
+        HIPCHK(c, hipMalloc(&c->info, (size_t)count * sizeof(int)));
+        c->info_cap = count;
+    }
+    rocblas_status st = rocsolver_dsyevd_strided_batched(c->blas, rocblas_evect_original, rocblas_fill_upper, P, A,
+                                                         P, (rocblas_stride)P * P, w, P, c->syev_e, P, c->info,
+                                                         count);
+    if (st != rocblas_status_success) {
+        c->err = std::string("rocsolver_dsyevd_strided_batched failed: ") + rocblas_status_to_string(st);
+        return 1;
+    }
+    return 0;
+}
+
+__global__ void k_pad_init(double* __restrict__ base, int P, const int32_t* __restrict__ nn) {
+    const int s = blockIdx.y;
+    const int n = nn[s];
+    double* A = base + (int64_t)s * P * P;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < (int64_t)P * P;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int r = (int)(e / P), q = (int)(e % P);
+        if (r < n && q < n) continue;
+        A[e] = (r == q) ? -1.0 : 0.0;
+    }
+}
+int pad_init(Ctx* c, double* base, int P, int count, const int32_t* d_n) {
+    if (count <= 0) return 0;
+    unsigned gx = grid_for((int64_t)P * P, 256, 256);
+    hipLaunchKernelGGL(k_pad_init, dim3(gx, count), dim3(256), 0, c->stream, base, P, d_n);
+    LAUNCHCHK(c);
+    return 0;
+}
+
 // one block per kept column: sign so that the first largest-|.| entry is positive
-__global__ void __launch_bounds__(256) k_gather_evecs(const double* __restrict__ E, int n,
+__global__ void __launch_bounds__(256) k_gather_evecs(const double* __restrict__ E, int n, int stride,
                                                       const int32_t* __restrict__ idx, int k,
                                                       double* __restrict__ U) {
     __shared__ double bv[256];
     __shared__ int bi[256];
     const int col = blockIdx.x;
-    const double* e = E + (int64_t)idx[col] * n;
+    const double* e = E + (int64_t)idx[col] * stride;
     double best = -1.0;
     int besti = 0x7fffffff;
     for (int r = threadIdx.x; r < n; r += blockDim.x) {
@@ -952,9 +1072,9 @@ __global__ void __launch_bounds__(256) k_gather_evecs(const double* __restrict__
     const double sg = e[bi[0]] < 0.0 ? -1.0 : 1.0;
     for (int r = threadIdx.x; r < n; r += blockDim.x) U[(int64_t)r * k + col] = sg * e[r];
 }
-int gather_evecs(Ctx* c, const double* E, int n, const int32_t* idx, int k, double* U) {
+int gather_evecs(Ctx* c, const double* E, int n, int stride, const int32_t* idx, int k, double* U) {
     if (k <= 0) return 0;
-    hipLaunchKernelGGL(k_gather_evecs, dim3(k), dim3(256), 0, c->stream, E, n, idx, k, U);
+    hipLaunchKernelGGL(k_gather_evecs, dim3(k), dim3(256), 0, c->stream, E, n, stride, idx, k, U);
     LAUNCHCHK(c);
     return 0;
 }

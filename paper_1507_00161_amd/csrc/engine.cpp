@@ -18,7 +18,9 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <numeric>
+#include <queue>
 #include <set>
 #include <sstream>
 
@@ -164,7 +166,12 @@ dmrg_status Engine::run_gemm(int prec, BufTable bufs, const GemmPlan& p, int cpr
         TRY(ensure_partials(p.nslots));
         bufs[dmrgdev::kPartialBuf] = partial_.p;
     }
-    DEV(dmrgdev::gemm(dev_, prec, cprec, bufs.data(), p.tasks.as<GemmTask>(), p.ntasks, p.chunks.as<GemmChunk>()));
+    dmrgdev::Sched sc;
+    sc.wg_off = p.wg_off.as<int32_t>();
+    sc.nwg = p.nwg;
+    sc.nfull = p.nfull;
+    sc.ntasks = p.ntasks;
+    DEV(dmrgdev::gemm(dev_, prec, cprec, bufs.data(), p.tasks.as<GemmTask>(), sc, p.chunks.as<GemmChunk>()));
     if (p.nreds)
         DEV(dmrgdev::gemm_reduce(dev_, cprec, bufs.data(), p.reds.as<dmrgdev::RedTask>(), p.nreds));
     return DMRG_OK;
@@ -176,10 +183,93 @@ dmrg_status Engine::ensure_partials(int64_t slots) {
     return alloc_buf(partial_, need);
 }
 
+// Static schedule of a persistent GEMM launch.  Estimated task cost: its K
+// slices plus a fixed start/epilogue overhead.  Output blocks (all their
+// tiles and split-K parts) are dealt to the 8 XCDs longest-first onto the
+// least-loaded XCD, so that the tiles sharing A rows or B columns share one
+// L2; blocks larger than 1/64 of the launch are dealt tile by tile.  Within
+// an XCD, tasks go longest-first to its least-loaded work-group.  Tasks
+// without chunks (pure clears) are moved behind all others.  The task vector
+// is reordered in place: work-group w = 8 j + x runs [wg_off[w], wg_off[w+1]).
+static void schedule_tasks(const GB& g, std::vector<GemmTask>& tasks, const std::vector<int32_t>& owner,
+                           std::vector<int32_t>& wg_off, int& nwg, int& nfull) {
+    const int64_t n = (int64_t)tasks.size();
+    std::vector<double> cost(n, 0.0);
+    std::vector<int64_t> full, empty;
+    double total = 0.0;
+    for (int64_t t = 0; t < n; ++t) {
+        if (tasks[t].chunk_begin == tasks[t].chunk_end) {
+            empty.push_back(t);
+            continue;
+        }
+        double c = 64.0;
+        for (int32_t k = tasks[t].chunk_begin; k < tasks[t].chunk_end; ++k)
+            c += 32.0 * std::ceil(g.chunks[k].K / 32.0) + 8.0;
+        cost[t] = c;
+        total += c;
+        full.push_back(t);
+    }
+    nfull = (int)full.size();
+    const int gw = (int)std::max<int64_t>(1, std::min<int64_t>(128, (nfull + 7) / 8));
+    nwg = 8 * gw;
+    // units dealt to XCDs: whole output blocks, or single tasks of big blocks
+    std::map<int32_t, std::vector<int64_t>> by_block;
+    for (int64_t t : full) by_block[owner[t]].push_back(t);
+    struct Unit {
+        double c;
+        std::vector<int64_t> ts;
+    };
+    std::vector<Unit> units;
+    for (auto& kv : by_block) {
+        double c = 0.0;
+        for (int64_t t : kv.second) c += cost[t];
+        if (c <= total / 64.0) {
+            units.push_back({c, kv.second});
+        } else {
+            for (int64_t t : kv.second) units.push_back({cost[t], {t}});
+        }
+    }
+    std::stable_sort(units.begin(), units.end(), [](const Unit& a, const Unit& b) { return a.c > b.c; });
+    std::vector<std::vector<int64_t>> xcd(8);
+    std::array<double, 8> xload{};
+    for (auto& u : units) {
+        int best = 0;
+        for (int x = 1; x < 8; ++x)
+            if (xload[x] < xload[best]) best = x;
+        xload[best] += u.c;
+        xcd[best].insert(xcd[best].end(), u.ts.begin(), u.ts.end());
+    }
+    std::vector<std::vector<int64_t>> wl(nwg);
+    for (int x = 0; x < 8; ++x) {
+        auto& v = xcd[x];
+        std::stable_sort(v.begin(), v.end(), [&](int64_t a, int64_t b) { return cost[a] > cost[b]; });
+        typedef std::pair<double, int> QE;
+        std::priority_queue<QE, std::vector<QE>, std::greater<QE>> q;
+        for (int j = 0; j < gw; ++j) q.push({0.0, j});
+        for (int64_t t : v) {
+            QE e = q.top();
+            q.pop();
+            wl[8 * e.second + x].push_back(t);
+            q.push({e.first + cost[t], e.second});
+        }
+    }
+    std::vector<GemmTask> out;
+    out.reserve(n);
+    wg_off.assign(nwg + 1, 0);
+    for (int w = 0; w < nwg; ++w) {
+        wg_off[w] = (int32_t)out.size();
+        for (int64_t t : wl[w]) out.push_back(tasks[t]);
+    }
+    wg_off[nwg] = (int32_t)out.size();
+    for (int64_t t : empty) out.push_back(tasks[t]);
+    tasks.swap(out);
+}
+
 static dmrg_status finish_plan(Engine& e, GB& g, GemmPlan& p) {
     using dmrgdev::kTileM;
     using dmrgdev::kTileN;
     std::vector<GemmTask> tasks;
+    std::vector<int32_t> owner;   // output block of each task
     std::vector<dmrgdev::RedTask> reds;
     // total work in K units, tile by tile
     double work = 0.0;
@@ -233,6 +323,7 @@ static dmrg_status finish_plan(Engine& e, GB& g, GemmPlan& p) {
                     t.beta = (uint8_t)ob.beta;
                     t.c_local = 0;
                     tasks.push_back(t);
+                    owner.push_back((int32_t)(&ob - g.obs.data()));
                     continue;
                 }
                 dmrgdev::RedTask r{};
@@ -254,11 +345,14 @@ static dmrg_status finish_plan(Engine& e, GB& g, GemmPlan& p) {
                     u.beta = 0;
                     u.c_local = 1;
                     tasks.push_back(u);
+                    owner.push_back((int32_t)(&ob - g.obs.data()));
                     ++slot;
                 }
             }
     }
     (void)ntiles;
+    std::vector<int32_t> wg_off;
+    schedule_tasks(g, tasks, owner, wg_off, p.nwg, p.nfull);
     p.ntasks = (int)tasks.size();
     p.nreds = (int)reds.size();
     p.nslots = slot;
@@ -266,6 +360,8 @@ static dmrg_status finish_plan(Engine& e, GB& g, GemmPlan& p) {
     p.flops = g.flops;
     p.elems = g.elems;
     dmrg_status st = e.upload(p.tasks, tasks);
+    if (st) return st;
+    st = e.upload(p.wg_off, wg_off);
     if (st) return st;
     st = e.upload(p.reds, reds);
     if (st) return st;
@@ -1709,20 +1805,12 @@ dmrg_status Engine::initialize(int D) {
 // rho of the S (left = true) or E sectors present in psi, with the
 // perturbation alpha * sum_O (O psi)(O psi)^T over c+ and c of the block's
 // sites.  rho blocks are dense (d x d) at roff[x] for psi block x.
-dmrg_status Engine::density_matrix(Bond& B, bool left, double alpha, Buf& rho, std::vector<int64_t>& roff,
-                                   std::vector<int>& rdim) {
+dmrg_status Engine::density_matrix(Bond& B, bool left, double alpha, Buf& rho, const std::vector<int64_t>& roff,
+                                   const std::vector<int>& rld) {
     const Enl &S = B.S, &E = B.E;
     int nb = (int)B.pm_S.size();
-    roff.assign(nb, 0);
-    rdim.assign(nb, 0);
-    int64_t tot = 0;
-    for (int x = 0; x < nb; ++x) {
-        int d = left ? S.md[B.pm_S[x]] : E.md[B.pm_E[x]];
-        rdim[x] = d;
-        roff[x] = tot;
-        tot += ((int64_t)d * d + 31) / 32 * 32;
-    }
-    TRY(alloc_buf(rho, std::max<int64_t>(tot, 1) * sizeof(double)));
+    std::vector<int> rdim(nb);
+    for (int x = 0; x < nb; ++x) rdim[x] = left ? S.md[B.pm_S[x]] : E.md[B.pm_E[x]];
     // bufs: 0 psi, 1 ops, 2 Phi, 3 rho
     std::vector<std::vector<GemmChunk>> lists(nb);
     GB g1;
@@ -1792,7 +1880,7 @@ dmrg_status Engine::density_matrix(Bond& B, bool left, double alpha, Buf& rho, s
     for (int x = 0; x < nb; ++x) {
         g2.begin();
         for (auto& c : lists[x]) g2.chunks.push_back(c);
-        g2.end(3, roff[x], rdim[x], rdim[x], rdim[x], 0);
+        g2.end(3, roff[x], rld[x], rdim[x], rdim[x], 0);
     }
     Buf phib;
     TRY(alloc_buf(phib, std::max<int64_t>(phi, 1) * sizeof(double)));
@@ -1853,21 +1941,64 @@ dmrg_status Engine::truncate_and_move(int D, double alpha, double* disc) {
         chosen = ch2;
         TRY(upload(blk->iso, flat));
     } else {
-        Buf rho;
-        std::vector<int64_t> roff;
-        std::vector<int> rdim;
-        TRY(density_matrix(B, left, alpha, rho, roff, rdim));
-        Buf w;
-        int64_t wtot = 0;
-        std::vector<int64_t> woff(nb);
+        // sector density matrices in padded slots grouped by size; one batched
+        // eigensolver call per size
+        std::vector<int> rdim(nb), rld(nb), slot(nb);
+        std::vector<int64_t> roff(nb), woff(nb);
+        std::map<int, std::vector<int>> buckets;
         for (int x = 0; x < nb; ++x) {
-            woff[x] = wtot;
-            wtot += rdim[x];
+            rdim[x] = left ? B.S.md[B.pm_S[x]] : B.E.md[B.pm_E[x]];
+            static const int sizes[] = {8, 16, 32, 48, 64, 96, 128, 192, 256, 384, 512, 768, 1024, 1536, 2048,
+                                        3072, 4096, 6144, 8192};
+            int P = rdim[x];
+            for (int z : sizes)
+                if (z >= rdim[x]) {
+                    P = z;
+                    break;
+                }
+            rld[x] = P;
+            buckets[P].push_back(x);
         }
+        int64_t tot = 0, wtot = 0;
+        std::vector<std::array<int64_t, 4>> bk;   // P, count, A offset, w offset
+        std::vector<int32_t> nlist;
+        std::vector<int64_t> nlist_off;
+        for (auto& kv : buckets) {
+            const int P = kv.first;
+            bk.push_back({P, (int64_t)kv.second.size(), tot, wtot});
+            nlist_off.push_back((int64_t)nlist.size());
+            for (size_t q = 0; q < kv.second.size(); ++q) {
+                int x = kv.second[q];
+                slot[x] = (int)q;
+                roff[x] = tot + (int64_t)q * P * P;
+                woff[x] = wtot + (int64_t)q * P + (P - rdim[x]);   // real eigenvalues are the last n
+                nlist.push_back(rdim[x]);
+            }
+            tot += (int64_t)P * P * kv.second.size();
+            wtot += (int64_t)P * kv.second.size();
+        }
+        Buf rho, w, nbuf;
+        TRY(alloc_buf(rho, std::max<int64_t>(tot, 1) * sizeof(double)));
         TRY(alloc_buf(w, std::max<int64_t>(wtot, 1) * sizeof(double)));
-        for (int x = 0; x < nb; ++x) DEV(dmrgdev::syevd(dev_, rdim[x], rho.d() + roff[x], w.d() + woff[x]));
-        std::vector<double> hw(wtot);
-        DEV(dmrgdev::d2h(dev_, hw.data(), w.p, wtot * sizeof(double)));
+        TRY(upload(nbuf, nlist));
+        for (size_t y = 0; y < bk.size(); ++y)
+            DEV(dmrgdev::pad_init(dev_, rho.d() + bk[y][2], (int)bk[y][0], (int)bk[y][1],
+                                  nbuf.as<int32_t>() + nlist_off[y]));
+        double td = now();
+        TRY(density_matrix(B, left, alpha, rho, roff, rld));
+        acc_.density_seconds += now() - td;
+        td = now();
+        for (auto& b4 : bk)
+            DEV(dmrgdev::syevd_batched(dev_, (int)b4[0], (int)b4[1], rho.d() + b4[2], w.d() + b4[3]));
+        std::vector<double> hwall(wtot);
+        DEV(dmrgdev::d2h(dev_, hwall.data(), w.p, wtot * sizeof(double)));
+        // compact the real eigenvalues: block x owns hw[woff[x] .. woff[x] + rdim[x])
+        std::vector<double> hw;
+        for (int x = 0; x < nb; ++x) {
+            const int64_t src = woff[x];
+            woff[x] = (int64_t)hw.size();
+            hw.insert(hw.end(), hwall.begin() + src, hwall.begin() + src + rdim[x]);
+        }
         double tr = 0.0;
         for (double v : hw) tr += v;
         struct Wt {
@@ -1875,8 +2006,8 @@ dmrg_status Engine::truncate_and_move(int D, double alpha, double* disc) {
             int x, e;
         };
         std::vector<Wt> all;
-        // in merged-sector order, eigenvalues ascending within a sector (stable sort below
-        // orders equal weights by sector then index, as the reference listing does)
+        // listed by sector, eigenvalues ascending within a sector; the stable sort keeps
+        // equal weights in that order
         for (int x = 0; x < nb; ++x)
             for (int e = 0; e < rdim[x]; ++e) all.push_back({hw[woff[x] + e] / tr, x, e});
         std::stable_sort(all.begin(), all.end(), [](const Wt& a, const Wt& c) { return a.w > c.w; });
@@ -1908,17 +2039,18 @@ dmrg_status Engine::truncate_and_move(int D, double alpha, double* disc) {
             kdim.push_back((int)s.size());
             iso_off.push_back(utot);
             jobs.push_back({x, (int64_t)idx.size(), (int64_t)s.size()});
-            idx.insert(idx.end(), s.begin(), s.end());
+            for (int e : s) idx.push_back(e + (rld[x] - rdim[x]));   // eigenvector row in the padded slot
             utot += ((int64_t)rdim[x] * s.size() + 31) / 32 * 32;
         }
         TRY(upload(idxb, idx));
         TRY(alloc_buf(blk->iso, std::max<int64_t>(utot, 1) * sizeof(double)));
         for (size_t y = 0; y < jobs.size(); ++y) {
             int x = (int)jobs[y][0];
-            DEV(dmrgdev::gather_evecs(dev_, rho.d() + roff[x], rdim[x], idxb.as<int32_t>() + jobs[y][1],
+            DEV(dmrgdev::gather_evecs(dev_, rho.d() + roff[x], rdim[x], rld[x], idxb.as<int32_t>() + jobs[y][1],
                                       (int)jobs[y][2], blk->iso.d() + iso_off[y]));
         }
         DEV(dmrgdev::sync(dev_));
+        acc_.eig_seconds += now() - td;
     }
     for (size_t y = 0; y < keep_m.size(); ++y) {
         blk->basis.add(en.mq[keep_m[y]], kdim[y]);
@@ -1927,7 +2059,9 @@ dmrg_status Engine::truncate_and_move(int D, double alpha, double* disc) {
     blk->iso_off = iso_off;
     blk->comp = en;
     bool normal_in = left ? normal_S(b) : !normal_S(b);
+    double trn = now();
     TRY(renormalize(en, left ? B.Sops : B.Eops, normal_in, *blk, keep_m, kdim));
+    acc_.renormalize_seconds += now() - trn;
     const Stored& base = left ? *L_[b] : *R_[b + 2];
     if (opt_.select_basis && base.has_cfg) {
         blk->has_cfg = true;
@@ -1950,6 +2084,7 @@ dmrg_status Engine::truncate_and_move(int D, double alpha, double* disc) {
     if (left) L_[b + 1] = std::move(blk);
     else R_[b + 1] = std::move(blk);
     TRY(setup_bond(nbond, NB));
+    double tpr = now();
     Bond& B2 = *NB;
     const Stored& nw = left ? *L_[b + 1] : *R_[b + 1];
     // Phi: left: U_m^T psi_m (k x dE) ; right: psi_m V (dS x k)
@@ -2059,6 +2194,7 @@ dmrg_status Engine::truncate_and_move(int D, double alpha, double* disc) {
     psi_ = std::move(npsi);
     if (!(std::sqrt(std::max(nn, 0.0)) >= 1e-10)) TRY(random_psi(B2, psi_));
     cur_ = std::move(NB);
+    acc_.predict_seconds += now() - tpr;
     return DMRG_OK;
 }
 

@@ -213,8 +213,9 @@ struct Term {
 using BufTable = std::array<void*, dmrgdev::kMaxBufs>;
 
 struct GemmPlan {
-    Buf tasks, chunks, reds;
+    Buf tasks, chunks, reds, wg_off;
     int ntasks = 0, nreds = 0;
+    int nwg = 0, nfull = 0;   // persistent work-groups; tasks with chunks
     int64_t nslots = 0;     // split-K partial tiles
     int64_t nchunks = 0;
     double flops = 0.0;
@@ -340,7 +341,7 @@ private:
     dmrg_status davidson(Bond& B, double* theta, int64_t* nlo, int64_t* n64, bool* conv);
     dmrg_status truncate_and_move(int D, double alpha, double* disc);
     dmrg_status density_matrix(Bond& B, bool left, double alpha, Buf& rho,
-                               std::vector<int64_t>& roff, std::vector<int>& rdim);
+                               const std::vector<int64_t>& roff, const std::vector<int>& rld);
     dmrg_status random_psi(Bond& B, Buf& out);
     dmrg_status run_gemm(int prec, BufTable bufs, const GemmPlan& p, int cprec = -1);
     dmrg_status ensure_partials(int64_t slots);
