@@ -22,6 +22,10 @@ const char* last_error(Ctx* c);
 void* alloc(Ctx* c, size_t bytes);          // nullptr on failure
 void release(Ctx* c, void* p);
 int h2d(Ctx* c, void* dst, const void* src, size_t bytes);   // returns when src may be reused
+// Stream-ordered upload: src is copied into a pinned staging arena at once
+// (src may be reused on return) and the device copy is queued on the stream.
+// The arena is recycled at the next full stream synchronisation.
+int h2d_async(Ctx* c, void* dst, const void* src, size_t bytes);
 int d2h(Ctx* c, void* dst, const void* src, size_t bytes);   // synchronous
 int d2d(Ctx* c, void* dst, const void* src, size_t bytes);
 int fill(Ctx* c, double* x, int64_t n, double v);
@@ -143,6 +147,7 @@ int syevd(Ctx* c, int n, double* A, double* w);
 // `count` symmetric P x P matrices at stride P*P, solved together (same
 // output convention; w at stride P).
 int syevd_batched(Ctx* c, int P, int count, double* A, double* w);
+int syevj_batched(Ctx* c, int P, int count, double* A, double* w);
 // Prepare padded slots: for slot s (base + s*P*P, real size n[s]) write 0
 // outside the leading n x n block and -1 on the padding diagonal, so the
 // padding eigenpairs are (-1, unit vectors of the padding rows).

@@ -37,6 +37,9 @@ struct Ctx {
     size_t syev_cap = 0;
     int* info = nullptr;
     size_t info_cap = 0;
+    // pinned staging arena for stream-ordered uploads
+    char* stage = nullptr;
+    size_t stage_cap = 0, stage_off = 0;
 };
 
 static int seterr(Ctx* c, const char* what, hipError_t e) {
@@ -103,6 +106,7 @@ void ctx_destroy(Ctx* c) {
     if (c->red) hipFree(c->red);
     if (c->syev_e) hipFree(c->syev_e);
     if (c->info) hipFree(c->info);
+    if (c->stage) hipHostFree(c->stage);
     if (c->own_stream) hipStreamDestroy(c->stream);
     delete c;
 }
@@ -121,25 +125,46 @@ void* alloc(Ctx* c, size_t bytes) {
 void release(Ctx*, void* p) {
     if (p) hipFree(p);
 }
+// every full synchronisation of the stream retires all queued staged copies
+static int stream_sync(Ctx* c) {
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->stage_off = 0;
+    return 0;
+}
 int h2d(Ctx* c, void* dst, const void* src, size_t bytes) {
     HIPCHK(c, hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, c->stream));
-    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return stream_sync(c);
+}
+int h2d_async(Ctx* c, void* dst, const void* src, size_t bytes) {
+    if (!bytes) return 0;
+    const size_t need = (bytes + 255) & ~(size_t)255;
+    if (c->stage_off + need > c->stage_cap) {
+        if (stream_sync(c)) return 1;
+        if (need > c->stage_cap) {
+            if (c->stage) HIPCHK(c, hipHostFree(c->stage));
+            c->stage = nullptr;
+            c->stage_cap = 0;
+            const size_t cap = std::max<size_t>(need, (size_t)64 << 20);
+            HIPCHK(c, hipHostMalloc((void**)&c->stage, cap, hipHostMallocDefault));
+            c->stage_cap = cap;
+        }
+    }
+    char* p = c->stage + c->stage_off;
+    memcpy(p, src, bytes);
+    c->stage_off += need;
+    HIPCHK(c, hipMemcpyAsync(dst, p, bytes, hipMemcpyHostToDevice, c->stream));
     return 0;
 }
 int d2h(Ctx* c, void* dst, const void* src, size_t bytes) {
     HIPCHK(c, hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(c, hipStreamSynchronize(c->stream));
-    return 0;
+    return stream_sync(c);
 }
 int d2d(Ctx* c, void* dst, const void* src, size_t bytes) {
     if (!bytes) return 0;
     HIPCHK(c, hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, c->stream));
     return 0;
 }
-int sync(Ctx* c) {
-    HIPCHK(c, hipStreamSynchronize(c->stream));
-    return 0;
-}
+int sync(Ctx* c) { return stream_sync(c); }
 int event_record(Ctx* c, int slot) {
     HIPCHK(c, hipEventRecord(c->ev[slot], c->stream));
     return 0;
@@ -218,59 +243,72 @@ template <> struct MmaTraits<float> {
 // (16 rows x 4 consecutive k per wave) then hit distinct banks.  Global
 // loads are coalesced along whichever dimension is contiguous in memory:
 // "along K" (A plain, B transposed) or "along M/N" (A transposed, B plain).
+// Operand loads go through raw buffer loads: a lane whose element lies
+// outside the operand (ragged tile edge or past the chunk's K) gets an offset
+// beyond the resource's range, and the hardware returns 0 for it without a
+// memory access.  Offsets are 32-bit byte offsets from the operand block's
+// own start (blocks are far below 2 GiB), so the per-element address work is
+// a few 32-bit operations.
+constexpr int kRecords = 0x7fffff00;   // resource range in bytes
+constexpr int kOutside = 0x7fffff80;   // an offset past the range
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, kRecords, 0x00020000);
+}
+template <class T> __device__ __forceinline__ T bload(__amdgpu_buffer_rsrc_t r, int off);
+template <> __device__ __forceinline__ float bload<float>(__amdgpu_buffer_rsrc_t r, int off) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+template <> __device__ __forceinline__ double bload<double>(__amdgpu_buffer_rsrc_t r, int off) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+
 template <class T, int BK>
 struct Slice {
     static constexpr int E = BK / 4;
     static constexpr int LDK = BK + (sizeof(T) == 8 ? 2 : 4);
     T v[E];
-    uint32_t ok;   // bit u: element u lies inside the operand
     T scale;
-    // Loads are issued unconditionally (an element outside the operand reads
-    // its first element instead) so that all of them are in flight at once;
-    // masking and scaling happen at the LDS store, after the MFMAs of the
-    // current slice.
     // element (r, k) at P[r*ld + k]: lane -> k = t % BK, rows t / BK + (256 / BK) u
-    __device__ __forceinline__ void load_k(const T* __restrict__ P, int ld, int r0, int rmax, int k0, int K,
-                                           T s, int tid) {
+    __device__ __forceinline__ void load_k(const T* P, int ld, int r0, int rmax, int k0, int K, T s, int tid) {
         constexpr int RS = NTH / BK;
         const int k = tid % BK, r = tid / BK;
         const bool kin = k0 + k < K;
+        const __amdgpu_buffer_rsrc_t rs = make_rsrc(P);
+        const int base = ((r0 + r) * ld + k0 + k) * (int)sizeof(T);
+        const int step = RS * ld * (int)sizeof(T);
         scale = s;
-        ok = 0;
 #pragma unroll
         for (int u = 0; u < E; ++u) {
-            const int rr = r + RS * u;
-            const bool in = kin && rr < rmax;
-            v[u] = P[in ? (int64_t)(r0 + rr) * ld + k0 + k : 0];
-            ok |= (uint32_t)in << u;
+            const bool in = kin && r + RS * u < rmax;
+            v[u] = bload<T>(rs, in ? base + u * step : kOutside);
         }
     }
-    // element (r, k) at P[k*ld + r]: lane -> r = t % 64, k = t / 64 + 4 u
-    __device__ __forceinline__ void load_m(const T* __restrict__ P, int ld, int r0, int rmax, int k0, int K,
-                                           T s, int tid) {
-        const int r = tid & 63, k = tid >> 6;
+    // element (r, k) at P[k*ld + r]: lane -> r = t % 16 + 16 (t / 64), k = (t / 16) % 4 + 4 u
+    // (16 consecutive r per row for coalescing; a wave's LDS stores then fall
+    // in 64 different banks)
+    __device__ __forceinline__ void load_m(const T* P, int ld, int r0, int rmax, int k0, int K, T s, int tid) {
+        const int r = (tid & 15) + 16 * (tid >> 6), k = (tid >> 4) & 3;
         const bool rin = r < rmax;
+        const __amdgpu_buffer_rsrc_t rs = make_rsrc(P);
+        const int base = ((k0 + k) * ld + r0 + r) * (int)sizeof(T);
+        const int step = 4 * ld * (int)sizeof(T);
         scale = s;
-        ok = 0;
 #pragma unroll
         for (int u = 0; u < E; ++u) {
-            const int kk = k + 4 * u;
-            const bool in = rin && k0 + kk < K;
-            v[u] = P[in ? (int64_t)(k0 + kk) * ld + r0 + r : 0];
-            ok |= (uint32_t)in << u;
+            const bool in = rin && k0 + k + 4 * u < K;
+            v[u] = bload<T>(rs, in ? base + u * step : kOutside);
         }
     }
-    __device__ __forceinline__ T get(int u) const { return ((ok >> u) & 1u) ? v[u] * scale : T(0); }
     __device__ __forceinline__ void store_k(T* __restrict__ S, int tid) const {
         constexpr int RS = NTH / BK;
         const int k = tid % BK, r = tid / BK;
 #pragma unroll
-        for (int u = 0; u < E; ++u) S[(r + RS * u) * LDK + k] = get(u);
+        for (int u = 0; u < E; ++u) S[(r + RS * u) * LDK + k] = v[u] * scale;
     }
     __device__ __forceinline__ void store_m(T* __restrict__ S, int tid) const {
-        const int r = tid & 63, k = tid >> 6;
+        const int r = (tid & 15) + 16 * (tid >> 6), k = (tid >> 4) & 3;
 #pragma unroll
-        for (int u = 0; u < E; ++u) S[r * LDK + k + 4 * u] = get(u);
+        for (int u = 0; u < E; ++u) S[r * LDK + k + 4 * u] = v[u] * scale;
     }
 };
 
@@ -405,12 +443,29 @@ __global__ void __launch_bounds__(NTH, 4) k_gemm(Bufs bufs, const GemmTask* __re
 #pragma unroll
                 for (int b = 0; b < 2; ++b) bv[s4][b] = Bb[(wn + b * 16 + fr) * LDK + 4 * s4 + fk];
             }
+            // MFMAs of 16 x 16 blocks that lie wholly outside the tile, and
+            // 4-deep K steps past the chunk's end, are skipped (wave-uniform
+            // tests): ragged sector blocks cost what they contain.
+            const int kv = ch.K - k0;
+            const bool am1 = wm + 16 < tk.mt, bm1 = wn + 16 < tk.nt;
+            if (kv >= BK && am1 && bm1) {
 #pragma unroll
-            for (int s4 = 0; s4 < BK / 4; ++s4)
+                for (int s4 = 0; s4 < BK / 4; ++s4)
 #pragma unroll
-                for (int a = 0; a < 2; ++a)
+                    for (int a = 0; a < 2; ++a)
 #pragma unroll
-                    for (int b = 0; b < 2; ++b) acc[a][b] = MmaTraits<T>::mma(av[s4][a], bv[s4][b], acc[a][b]);
+                        for (int b = 0; b < 2; ++b) acc[a][b] = MmaTraits<T>::mma(av[s4][a], bv[s4][b], acc[a][b]);
+            } else if (wm < tk.mt && wn < tk.nt) {
+#pragma unroll
+                for (int s4 = 0; s4 < BK / 4; ++s4) {
+                    if (4 * s4 < kv) {
+                        acc[0][0] = MmaTraits<T>::mma(av[s4][0], bv[s4][0], acc[0][0]);
+                        if (bm1) acc[0][1] = MmaTraits<T>::mma(av[s4][0], bv[s4][1], acc[0][1]);
+                        if (am1) acc[1][0] = MmaTraits<T>::mma(av[s4][1], bv[s4][0], acc[1][0]);
+                        if (am1 && bm1) acc[1][1] = MmaTraits<T>::mma(av[s4][1], bv[s4][1], acc[1][1]);
+                    }
+                }
+            }
             if (newtask) {
                 epilogue(tk);
                 if (more) {
@@ -590,20 +645,29 @@ int gemm(Ctx* c, int ab, int cp, void* const* bufs, const GemmTask* tasks, const
 }
 
 // ------------------------------------------------------ split-K reduction
+// Block (task, y) sums elements [256 y, 256 y + 256) of one tile over its
+// slots in a fixed order (four interleaved partial sums, then combined), so
+// results are deterministic and many loads are in flight per thread.
 template <class TC>
 __global__ void __launch_bounds__(256) k_gemm_reduce(Bufs bufs, const RedTask* __restrict__ tasks) {
     const RedTask tk = tasks[blockIdx.x];
-    const TC* P = (const TC*)bufs.p[kPartialBuf] + (int64_t)tk.slot0 * TM * TN;
-    TC* D = (TC*)bufs.p[tk.dst_buf] + tk.dst_off;
-    for (int e = threadIdx.x; e < TM * TN; e += blockDim.x) {
-        const int r = e / TN, c = e % TN;
-        if (r >= tk.mt || c >= tk.nt) continue;
-        double s = 0.0;
-        for (int q = 0; q < tk.nslots; ++q) s += (double)P[(int64_t)q * TM * TN + e];
-        TC* d = D + (int64_t)r * tk.ld + c;
-        if (tk.beta) s += (double)*d;
-        *d = (TC)s;
+    const int e = blockIdx.y * 256 + threadIdx.x;
+    const int r = e / TN, c = e % TN;
+    if (r >= tk.mt || c >= tk.nt) return;
+    const TC* P = (const TC*)bufs.p[kPartialBuf] + (int64_t)tk.slot0 * TM * TN + e;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    int q = 0;
+    for (; q + 4 <= tk.nslots; q += 4) {
+        s0 += (double)P[(int64_t)q * TM * TN];
+        s1 += (double)P[(int64_t)(q + 1) * TM * TN];
+        s2 += (double)P[(int64_t)(q + 2) * TM * TN];
+        s3 += (double)P[(int64_t)(q + 3) * TM * TN];
     }
+    for (; q < tk.nslots; ++q) s0 += (double)P[(int64_t)q * TM * TN];
+    double s = (s0 + s1) + (s2 + s3);
+    TC* d = (TC*)bufs.p[tk.dst_buf] + tk.dst_off + (int64_t)r * tk.ld + c;
+    if (tk.beta) s += (double)*d;
+    *d = (TC)s;
 }
 
 int gemm_reduce(Ctx* c, int cp, void* const* bufs, const RedTask* tasks, int ntasks) {
@@ -611,9 +675,9 @@ int gemm_reduce(Ctx* c, int cp, void* const* bufs, const RedTask* tasks, int nta
     Bufs b;
     for (int i = 0; i < kMaxBufs; ++i) b.p[i] = bufs[i];
     if (cp == P_F64)
-        hipLaunchKernelGGL(k_gemm_reduce<double>, dim3(ntasks), dim3(256), 0, c->stream, b, tasks);
+        hipLaunchKernelGGL(k_gemm_reduce<double>, dim3(ntasks, TM * TN / 256), dim3(256), 0, c->stream, b, tasks);
     else if (cp == P_F32)
-        hipLaunchKernelGGL(k_gemm_reduce<float>, dim3(ntasks), dim3(256), 0, c->stream, b, tasks);
+        hipLaunchKernelGGL(k_gemm_reduce<float>, dim3(ntasks, TM * TN / 256), dim3(256), 0, c->stream, b, tasks);
     else {
         c->err = "split-K reduction supports FP64 and FP32 outputs";
         return 1;
@@ -1014,6 +1078,34 @@ int syevd_batched(Ctx* c, int P, int count, double* A, double* w) {
                                                          count);
     if (st != rocblas_status_success) {
         c->err = std::string("rocsolver_dsyevd_strided_batched failed: ") + rocblas_status_to_string(st);
+        return 1;
+    }
+    return 0;
+}
+
+// Jacobi variant of the batched solver (same layout and output order).
+int syevj_batched(Ctx* c, int P, int count, double* A, double* w) {
+    if (count <= 0 || P <= 0) return 0;
+    size_t need = (size_t)2 * count;   // residuals + sweep counts
+    if (c->syev_cap < need) {
+        if (c->syev_e) hipFree(c->syev_e);
+        c->syev_e = nullptr;
+        c->syev_cap = 0;
+        HIPCHK(c, hipMalloc(&c->syev_e, need * sizeof(double)));
+        c->syev_cap = need;
+    }
+    if (c->info_cap < (size_t)count) {
+        if (c->info) hipFree(c->info);
+        c->info = nullptr;
+        c->info_cap = 0;
+        HIPCHK(c, hipMalloc(&c->info, (size_t)count * sizeof(int)));
+        c->info_cap = count;
+    }
+    rocblas_status st = rocsolver_dsyevj_strided_batched(
+        c->blas, rocblas_esort_ascending, rocblas_evect_original, rocblas_fill_upper, P, A, P, (rocblas_stride)P * P,
+        0.0, c->syev_e, 100, (rocblas_int*)(c->syev_e + count), w, P, c->info, count);
+    if (st != rocblas_status_success) {
+        c->err = std::string("rocsolver_dsyevj_strided_batched failed: ") + rocblas_status_to_string(st);
         return 1;
     }
     return 0;

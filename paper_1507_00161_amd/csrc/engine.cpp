@@ -70,15 +70,63 @@ void Buf::reset() {
     bytes = 0;
 }
 
+// size classes 2^k (1 + j/8): at most 12.5% padding
+static size_t size_class(size_t b) {
+    if (b <= 4096) return 4096;
+    int k = 63 - __builtin_clzll((unsigned long long)b);
+    size_t step = (size_t)1 << (k - 3);
+    return (b + step - 1) / step * step;
+}
+
 void* Engine::dalloc(size_t bytes) {
-    if (opt_.mem_cap_bytes && mem_used_ + bytes > opt_.mem_cap_bytes) return nullptr;
-    void* p = dmrgdev::alloc(dev_, bytes ? bytes : 8);
-    if (p) mem_used_ += bytes;
+    const size_t c = size_class(bytes);
+    // a cached block of this class, or of one of the next two classes
+    auto it = cache_.lower_bound(c);
+    if (it != cache_.end() && it->first <= c + c / 4) {
+        void* p = it->second;
+        const size_t s = it->first;
+        cache_.erase(it);
+        cached_ -= s;
+        live_[p] = s;
+        return p;
+    }
+    if (opt_.mem_cap_bytes && mem_used_ + c > opt_.mem_cap_bytes) trim_cache(0);
+    if (opt_.mem_cap_bytes && mem_used_ + c > opt_.mem_cap_bytes) return nullptr;
+    void* p = dmrgdev::alloc(dev_, c);
+    if (!p && cached_) {
+        trim_cache(0);
+        p = dmrgdev::alloc(dev_, c);
+    }
+    if (!p) return nullptr;
+    mem_used_ += c;
+    live_[p] = c;
     return p;
 }
-void Engine::dfree(void* p, size_t bytes) {
-    dmrgdev::release(dev_, p);
-    mem_used_ -= bytes;
+void Engine::dfree(void* p, size_t) {
+    auto it = live_.find(p);
+    if (it == live_.end()) return;
+    const size_t s = it->second;
+    live_.erase(it);
+    if (dying_) {
+        dmrgdev::release(dev_, p);
+        mem_used_ -= s;
+        return;
+    }
+    cache_.emplace(s, p);
+    cached_ += s;
+    // bound the cache: release the largest blocks beyond 16 GiB
+    const size_t limit = (size_t)16 << 30;
+    if (cached_ > limit) trim_cache(limit / 2);
+}
+// release cached blocks, largest first, until at most `keep` bytes stay cached
+void Engine::trim_cache(size_t keep) {
+    while (cached_ > keep && !cache_.empty()) {
+        auto it = std::prev(cache_.end());
+        dmrgdev::release(dev_, it->second);
+        cached_ -= it->first;
+        mem_used_ -= it->first;
+        cache_.erase(it);
+    }
 }
 dmrg_status Engine::alloc_buf(Buf& b, size_t bytes) {
     b.reset();
@@ -95,15 +143,17 @@ dmrg_status Engine::alloc_buf(Buf& b, size_t bytes) {
 template <class T> dmrg_status Engine::upload(Buf& b, const std::vector<T>& v) {
     dmrg_status st = alloc_buf(b, std::max<size_t>(v.size() * sizeof(T), 8));
     if (st) return st;
-    if (!v.empty() && dmrgdev::h2d(dev_, b.p, v.data(), v.size() * sizeof(T)))
+    if (!v.empty() && dmrgdev::h2d_async(dev_, b.p, v.data(), v.size() * sizeof(T)))
         return fail(DMRG_ERR_DEVICE, dmrgdev::last_error(dev_));
     return DMRG_OK;
 }
 
 Engine::~Engine() {
+    dying_ = true;   // buffers released from here on go straight back to the device
     cur_.reset();
     L_.clear();
     R_.clear();
+    trim_cache(0);
 }
 
 #define TRY(x)                        \
@@ -185,83 +235,117 @@ dmrg_status Engine::ensure_partials(int64_t slots) {
 
 // Static schedule of a persistent GEMM launch.  Estimated task cost: its K
 // slices plus a fixed start/epilogue overhead.  Output blocks (all their
-// tiles and split-K parts) are dealt to the 8 XCDs longest-first onto the
-// least-loaded XCD, so that the tiles sharing A rows or B columns share one
-// L2; blocks larger than 1/64 of the launch are dealt tile by tile.  Within
-// an XCD, tasks go longest-first to its least-loaded work-group.  Tasks
-// without chunks (pure clears) are moved behind all others.  The task vector
-// is reordered in place: work-group w = 8 j + x runs [wg_off[w], wg_off[w+1]).
+// tiles and split-K parts, which are consecutive in `tasks`) are dealt to the
+// 8 XCDs, each onto the least-loaded XCD, so that the tiles sharing A rows
+// or B columns share one L2; blocks larger than 1/64 of the launch are dealt
+// tile by tile.  Within an XCD, each task goes to its least-loaded
+// work-group.  When work-groups get few tasks, both dealings go
+// longest-first.  Tasks without chunks (pure clears) are moved behind all
+// others.  The task vector is reordered in place: work-group
+// w = 8 j + x runs [wg_off[w], wg_off[w+1]).
 static void schedule_tasks(const GB& g, std::vector<GemmTask>& tasks, const std::vector<int32_t>& owner,
                            std::vector<int32_t>& wg_off, int& nwg, int& nfull) {
     const int64_t n = (int64_t)tasks.size();
-    std::vector<double> cost(n, 0.0);
-    std::vector<int64_t> full, empty;
+    std::vector<float> cost(n, 0.f);
     double total = 0.0;
+    int64_t nf = 0;
     for (int64_t t = 0; t < n; ++t) {
-        if (tasks[t].chunk_begin == tasks[t].chunk_end) {
-            empty.push_back(t);
-            continue;
-        }
+        const GemmTask& tk = tasks[t];
+        if (tk.chunk_begin == tk.chunk_end) continue;
         double c = 64.0;
-        for (int32_t k = tasks[t].chunk_begin; k < tasks[t].chunk_end; ++k)
-            c += 32.0 * std::ceil(g.chunks[k].K / 32.0) + 8.0;
-        cost[t] = c;
+        for (int32_t k = tk.chunk_begin; k < tk.chunk_end; ++k) c += 32.0 * ((g.chunks[k].K + 31) / 32) + 8.0;
+        cost[t] = (float)c;
         total += c;
-        full.push_back(t);
+        ++nf;
     }
-    nfull = (int)full.size();
-    const int gw = (int)std::max<int64_t>(1, std::min<int64_t>(128, (nfull + 7) / 8));
+    nfull = (int)nf;
+    const int gw = (int)std::max<int64_t>(1, std::min<int64_t>(128, (nf + 7) / 8));
     nwg = 8 * gw;
-    // units dealt to XCDs: whole output blocks, or single tasks of big blocks
-    std::map<int32_t, std::vector<int64_t>> by_block;
-    for (int64_t t : full) by_block[owner[t]].push_back(t);
+    // units: [begin, end) runs of one output block, or single tasks of big blocks
     struct Unit {
         double c;
-        std::vector<int64_t> ts;
+        int64_t b, e;
     };
     std::vector<Unit> units;
-    for (auto& kv : by_block) {
+    for (int64_t t = 0; t < n;) {
+        int64_t e = t;
         double c = 0.0;
-        for (int64_t t : kv.second) c += cost[t];
+        while (e < n && owner[e] == owner[t]) c += cost[e++];
         if (c <= total / 64.0) {
-            units.push_back({c, kv.second});
+            if (c > 0.0) units.push_back({c, t, e});
         } else {
-            for (int64_t t : kv.second) units.push_back({cost[t], {t}});
+            for (int64_t u = t; u < e; ++u)
+                if (cost[u] > 0.f) units.push_back({cost[u], u, u + 1});
         }
+        t = e;
     }
-    std::stable_sort(units.begin(), units.end(), [](const Unit& a, const Unit& b) { return a.c > b.c; });
-    std::vector<std::vector<int64_t>> xcd(8);
+    // Longest-first (LPT) dealing pays off when work-groups get few tasks; with
+    // many tasks per work-group, dealing in plan order to the least-loaded
+    // target balances as well and needs no sort.
+    const bool lpt = nf < 16 * (int64_t)nwg;
+    if (lpt)
+        std::sort(units.begin(), units.end(),
+                  [](const Unit& a, const Unit& b) { return a.c != b.c ? a.c > b.c : a.b < b.b; });
+    std::vector<int8_t> xcd_of(n, -1);
     std::array<double, 8> xload{};
-    for (auto& u : units) {
+    std::array<int64_t, 8> xcount{};
+    for (const Unit& u : units) {
         int best = 0;
         for (int x = 1; x < 8; ++x)
             if (xload[x] < xload[best]) best = x;
         xload[best] += u.c;
-        xcd[best].insert(xcd[best].end(), u.ts.begin(), u.ts.end());
+        for (int64_t t = u.b; t < u.e; ++t)
+            if (cost[t] > 0.f) {
+                xcd_of[t] = (int8_t)best;
+                ++xcount[best];
+            }
     }
-    std::vector<std::vector<int64_t>> wl(nwg);
-    for (int x = 0; x < 8; ++x) {
-        auto& v = xcd[x];
-        std::stable_sort(v.begin(), v.end(), [&](int64_t a, int64_t b) { return cost[a] > cost[b]; });
-        typedef std::pair<double, int> QE;
-        std::priority_queue<QE, std::vector<QE>, std::greater<QE>> q;
-        for (int j = 0; j < gw; ++j) q.push({0.0, j});
-        for (int64_t t : v) {
-            QE e = q.top();
-            q.pop();
-            wl[8 * e.second + x].push_back(t);
-            q.push({e.first + cost[t], e.second});
+    // tasks of each XCD, in dealing order
+    std::vector<int64_t> xoff(9, 0);
+    for (int x = 0; x < 8; ++x) xoff[x + 1] = xoff[x] + xcount[x];
+    std::vector<int64_t> order(nf);
+    {
+        std::vector<int64_t> fp(xoff.begin(), xoff.end() - 1);
+        if (lpt) {
+            for (const Unit& u : units)
+                for (int64_t t = u.b; t < u.e; ++t)
+                    if (xcd_of[t] >= 0) order[fp[xcd_of[t]]++] = t;
+        } else {
+            for (int64_t t = 0; t < n; ++t)
+                if (xcd_of[t] >= 0) order[fp[xcd_of[t]]++] = t;
         }
     }
-    std::vector<GemmTask> out;
-    out.reserve(n);
-    wg_off.assign(nwg + 1, 0);
-    for (int w = 0; w < nwg; ++w) {
-        wg_off[w] = (int32_t)out.size();
-        for (int64_t t : wl[w]) out.push_back(tasks[t]);
+    // per XCD: each task onto its least-loaded work-group
+    std::vector<int32_t> wg_of(n, -1);
+    typedef std::pair<double, int> QE;
+    std::vector<QE> heap;
+    auto cmp = [](const QE& a, const QE& b) { return a > b; };   // min-heap on (load, j)
+    for (int x = 0; x < 8; ++x) {
+        auto b = order.begin() + xoff[x], e = order.begin() + xoff[x + 1];
+        if (lpt)
+            std::sort(b, e, [&](int64_t p, int64_t q) { return cost[p] != cost[q] ? cost[p] > cost[q] : p < q; });
+        heap.clear();
+        for (int j = 0; j < gw; ++j) heap.push_back({0.0, j});
+        std::make_heap(heap.begin(), heap.end(), cmp);
+        for (auto it = b; it != e; ++it) {
+            std::pop_heap(heap.begin(), heap.end(), cmp);
+            QE& q = heap.back();
+            wg_of[*it] = 8 * q.second + x;
+            q.first += cost[*it];
+            std::push_heap(heap.begin(), heap.end(), cmp);
+        }
     }
-    wg_off[nwg] = (int32_t)out.size();
-    for (int64_t t : empty) out.push_back(tasks[t]);
+    // counting sort by work-group; within a work-group, tasks keep dealing order
+    wg_off.assign(nwg + 1, 0);
+    for (int64_t t = 0; t < n; ++t)
+        if (wg_of[t] >= 0) ++wg_off[wg_of[t] + 1];
+    for (int w = 0; w < nwg; ++w) wg_off[w + 1] += wg_off[w];
+    std::vector<GemmTask> out(n);
+    std::vector<int32_t> fillp(wg_off.begin(), wg_off.end() - 1);
+    for (int64_t t : order) out[fillp[wg_of[t]]++] = tasks[t];
+    int64_t z = nf;
+    for (int64_t t = 0; t < n; ++t)
+        if (cost[t] == 0.f) out[z++] = tasks[t];
     tasks.swap(out);
 }
 
@@ -281,8 +365,10 @@ static dmrg_status finish_plan(Engine& e, GB& g, GemmPlan& p) {
         work += kk * nt;
         ntiles += nt;
     }
-    const double target = 2048.0;   // work-groups that keep 256 CUs busy
-    const double kper = std::max(work / target, 1024.0);
+    // split-K parts: enough tasks for about 8 per persistent work-group, so
+    // that the static schedule balances; no part below 512 K
+    const double target = 8192.0;
+    const double kper = std::max(work / target, 512.0);
     int64_t slot = 0;
     for (const auto& ob : g.obs) {
         double kk = 0.0;

@@ -298,7 +298,17 @@ private:
         std::vector<std::vector<char>> p, n;
     };
     std::vector<Reach> pre_;     // pre_[b]: sites 0..b-1
-    size_t mem_used_ = 0;
+    // Stream-ordered device memory cache.  Every kernel and copy of a context
+    // runs on its one stream, so a freed block can be handed out again at once:
+    // later users are ordered after earlier ones.  This keeps hipFree (which
+    // waits for the device) out of the sweep.  Declared before every Buf so
+    // that it outlives them.
+    size_t mem_used_ = 0;        // live + cached bytes
+    size_t cached_ = 0;
+    bool dying_ = false;
+    std::multimap<size_t, void*> cache_;
+    std::unordered_map<void*, size_t> live_;
+    void trim_cache(size_t keep);
 
     // DMRG state
     bool init_ = false;
