@@ -109,6 +109,114 @@ def cpu_baseline(budget_s: float = 20.0):
                       f"merged-sector matmul flops / time in H_eff products"}
 
 
+KERNEL_SRC = os.path.join(ROOT, "paper_1507_00161_amd", "csrc", "device.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_heff_y_f32_pf_8p8n_D2048_traffic.txt")
+
+
+def source_sha() -> str:
+    import hashlib
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per launch of the phase-2 kernel from the committed counter
+    summary, or None when the kernel source changed since it was taken."""
+    try:
+        kv = dict(l.strip().split("=", 1) for l in open(TRAFFIC_FILE) if "=" in l and not l.startswith("#"))
+    except OSError:
+        return None
+    if kv.get("device_hip_sha256") != source_sha():
+        return None
+    return float(kv["hbm_bytes_per_launch"])
+
+
+def _csv_rows(path):
+    import csv
+    with open(path) as f:
+        return list(csv.DictReader(f))
+
+
+def _find(d, suffix):
+    import glob
+    hits = sorted(glob.glob(os.path.join(d, "**", "*" + suffix), recursive=True))
+    if not hits:
+        raise SystemExit(f"no *{suffix} under {d}")
+    return hits[0]
+
+
+def _short(name):
+    return name.split("(")[0].replace("void ", "").replace("dmrgdev::", "")
+
+
+def summarize_trace(d, bench_json, kernel):
+    """Markdown summary of a `rocprofv3 --kernel-trace --stats` run of this
+    benchmark: the kernel table, and the average duration of `kernel` over the
+    timed sweeps (its last N dispatches, N from the benchmark's own line)."""
+    b = json.loads([l for l in open(bench_json) if l.startswith("{")][-1])
+    n = int(b["roofline"]["launches"])
+    stats = _csv_rows(_find(d, "kernel_stats.csv"))
+    trace = _csv_rows(_find(d, "kernel_trace.csv"))
+    sel = [r for r in trace if _short(r["Kernel_Name"]) == kernel]
+    sel.sort(key=lambda r: int(r["Start_Timestamp"]))
+    last = sel[-n:]
+    avg = sum(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]) for r in last) / max(len(last), 1)
+    out = [f"- benchmark line: value {b['value']:.2f} {b['unit']}, ms_per_step {b['ms_per_step']:.0f}, "
+           f"roofline.launch_ms {b['roofline']['launch_ms']:.4f} over {n} launches",
+           f"- `{kernel}`: {len(sel)} dispatches in the run; mean of the last {len(last)} "
+           f"(the timed sweeps) = {avg / 1e6:.4f} ms",
+           "", "| kernel | calls | total s | avg us | % |", "|---|---|---|---|---|"]
+    for r in sorted(stats, key=lambda r: -float(r["TotalDurationNs"]))[:15]:
+        out.append(f"| `{_short(r['Name'])[:70]}` | {r['Calls']} | {float(r['TotalDurationNs']) / 1e9:.3f} | "
+                   f"{float(r['AverageNs']) / 1e3:.1f} | {float(r['Percentage']):.1f} |")
+    print("\n".join(out))
+
+
+def summarize_counters(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, bench_json, kernel, copy_mib):
+    """HBM traffic per launch of `kernel` over the timed sweeps from two PMC
+    runs (FETCH_SIZE, WRITE_SIZE in KiB per dispatch), each scaled by what the
+    same counter reads for a plain copy of known size."""
+    b = json.loads([l for l in open(bench_json) if l.startswith("{")][-1])
+    n = int(b["roofline"]["launches"])
+
+    def per_dispatch(d, counter, match):
+        rows = [r for r in _csv_rows(_find(d, "counter_collection.csv"))
+                if r["Counter_Name"] == counter and match(_short(r["Kernel_Name"]))]
+        by = {}
+        for r in rows:
+            k = int(r["Dispatch_Id"])
+            by.setdefault(k, [int(r["Start_Timestamp"]), 0.0])
+            by[k][1] += float(r["Counter_Value"])
+        return [v for _, v in sorted(by.values())]
+
+    fk = per_dispatch(fetch_dir, "FETCH_SIZE", lambda s: s == kernel)[-n:]
+    wk = per_dispatch(write_dir, "WRITE_SIZE", lambda s: s == kernel)[-n:]
+    cf = max(per_dispatch(copy_fetch_dir, "FETCH_SIZE", lambda s: "copy" in s.lower() or "elementwise" in s))
+    cw = max(per_dispatch(copy_write_dir, "WRITE_SIZE", lambda s: "copy" in s.lower() or "elementwise" in s))
+    kib = copy_mib * 1024.0
+    sf, sw = kib / cf, kib / cw
+    fetch = sum(fk) / len(fk) * 1024 * sf
+    write = sum(wk) / len(wk) * 1024 * sw
+    print(f"# {kernel}: HBM traffic per launch over the timed sweeps ({len(fk)} launches)")
+    print(f"# copy reference: {copy_mib} MiB copy reads FETCH_SIZE {cf:.0f} KiB (scale {sf:.3f}), "
+          f"WRITE_SIZE {cw:.0f} KiB (scale {sw:.3f})")
+    print(f"# algorithmic bytes per launch {b['roofline']['algorithmic_gb_per_launch'] * 1e9:.4g}")
+    print(f"fetch_bytes_per_launch={fetch:.6g}")
+    print(f"write_bytes_per_launch={write:.6g}")
+    print(f"hbm_bytes_per_launch={fetch + write:.6g}")
+    print(f"device_hip_sha256={source_sha()}")
+
+
+def copy_reference(mib):
+    import torch
+    a = torch.ones(mib * (1 << 20) // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copied_bytes": a.numel() * 4}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -118,7 +226,22 @@ def main():
     ap.add_argument("--D", type=int, default=2048)
     ap.add_argument("--tol", type=float, default=1e-7)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--summarize-trace", metavar="DIR", help="summarise a rocprofv3 kernel-trace run")
+    ap.add_argument("--summarize-counters", nargs=4, metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE"),
+                    help="HBM traffic from rocprofv3 --pmc runs of this benchmark and of --copy-reference")
+    ap.add_argument("--bench-json", help="the benchmark line of the profiled run")
+    ap.add_argument("--kernel", default="k_heff_y<float, float, 32>")
+    ap.add_argument("--copy-reference", type=int, metavar="MIB", help="one plain device copy of MIB MiB")
     args = ap.parse_args()
+    if args.summarize_trace:
+        summarize_trace(args.summarize_trace, args.bench_json, args.kernel)
+        return
+    if args.summarize_counters:
+        summarize_counters(*args.summarize_counters, args.bench_json, args.kernel, args.copy_reference or 256)
+        return
+    if args.copy_reference:
+        copy_reference(args.copy_reference)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs one GPU; the multi-GPU path (term-sharded H_eff with an "
               "all-reduce of H_eff.psi) is designed but not built, so --gpus must be 1", file=sys.stderr)
@@ -139,9 +262,13 @@ def main():
     value = t["heff_flops"] / max(t["heff_seconds"], 1e-12) / 1e12
     # dominant kernel: the GEMM phase with the larger device time
     k = "gemm2" if t["gemm2_seconds"] >= t["gemm1_seconds"] else "gemm1"
-    kdt = t[f"{k}_seconds"] / max(t[f"{k}_launches"], 1)
-    kfl = t[f"{k}_flops"] / max(t[f"{k}_launches"], 1)
+    nl = max(t[f"{k}_launches"], 1)
+    kdt = t[f"{k}_seconds"] / nl
+    kfl = t[f"{k}_flops"] / nl
     achieved = kfl / max(kdt, 1e-12) / 1e12
+    ctype = {"fp64": "double, double, 16", "fp32": "float, float, 32"}.get(main_p, "")
+    kname = f"{'k_heff_y' if k == 'gemm2' else 'k_heff_z'}<{ctype}>" if ctype else "k_gemm_bf16"
+    traffic = measured_traffic() if (k == "gemm2" and main_p == "fp32") else None
     out = {
         "metric": "Davidson H_eff·psi TFLOP/s + sweep time at D=2048, mixed vs FP64, |dE|<1e-6",
         "value": value,
@@ -158,11 +285,13 @@ def main():
         "config": {"workload": "pf_8p8n: pf shell, 40 sites, 8p+8n, 2M=0, random eps/Vbar seed 150703, "
                                f"natural order, D ramp 512,512,1024,1024 then D={args.D}",
                    "D": args.D, "precision": main_p, "davidson_tol": args.tol},
-        "roofline": {"bound": "mfma", "kernel": f"k_gemm ({'phase 2: op(A) Z' if k == 'gemm2' else 'phase 1: psi op(B)^T'})",
+        "roofline": {"bound": "mfma", "kernel": kname,
                      "achieved": achieved, "peak": PEAK[main_p], "unit": "TFLOP/s",
-                     "frac": achieved / PEAK[main_p], "traffic": None,
-                     "launch_ms": 1e3 * kdt, "algorithmic_gflop_per_launch": kfl / 1e9,
-                     "algorithmic_gb_per_launch": t[f"{k}_bytes"] / max(t[f"{k}_launches"], 1) / 1e9},
+                     "frac": achieved / PEAK[main_p], "traffic": traffic,
+                     "launch_ms": 1e3 * kdt, "launches": int(t[f"{k}_launches"]),
+                     "algorithmic_gflop_per_launch": kfl / 1e9,
+                     "algorithmic_gb_per_launch": t[f"{k}_bytes"] / nl / 1e9,
+                     "split_k_reduce_ms_per_launch": 1e3 * t.get("reduce_seconds", 0.0) / nl},
     }
     for p, r in res.items():
         tt = r["tot"]

@@ -82,11 +82,15 @@ typedef struct dmrg_sweep_stats {
     int32_t status;           /* per-context status (dmrg_sweep_many) */
     int32_t steps;            /* two-site steps done */
     /* per-kernel accounting of the H_eff.psi grouped GEMMs (HIP events on the
-     * context stream): phase 1 forms psi op(B)^T, phase 2 accumulates op(A) Z */
+     * context stream): phase 1 (kernel k_heff_z) forms psi op(B)^T, phase 2
+     * (k_heff_y) accumulates op(A) Z.  Only launches in the context's working
+     * precision are counted (FP64 in DMRG_FP64 mode, the reduced precision in
+     * the mixed modes); the split-K reduction after phase 2 is timed apart. */
     int64_t gemm1_launches, gemm2_launches;
     double gemm1_seconds, gemm2_seconds;
     double gemm1_flops, gemm2_flops;
     double gemm1_bytes, gemm2_bytes;   /* algorithmic operand + result bytes */
+    double reduce_seconds;             /* split-K reductions of those launches */
 } dmrg_sweep_stats;
 
 typedef struct dmrg_ctx dmrg_ctx;

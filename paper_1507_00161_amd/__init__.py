@@ -47,7 +47,8 @@ class SweepStats(ctypes.Structure):
                 ("gemm1_launches", ctypes.c_int64), ("gemm2_launches", ctypes.c_int64),
                 ("gemm1_seconds", ctypes.c_double), ("gemm2_seconds", ctypes.c_double),
                 ("gemm1_flops", ctypes.c_double), ("gemm2_flops", ctypes.c_double),
-                ("gemm1_bytes", ctypes.c_double), ("gemm2_bytes", ctypes.c_double)]
+                ("gemm1_bytes", ctypes.c_double), ("gemm2_bytes", ctypes.c_double),
+                ("reduce_seconds", ctypes.c_double)]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}

@@ -79,8 +79,10 @@ struct Sched {
     const int32_t* wg_off;
     int32_t nwg, nfull, ntasks;
 };
+// kind: which H_eff phase a launch is (only the kernel's name differs, for profiles)
+enum GemmKind { GK_OTHER = 0, GK_HEFF_Z = 1, GK_HEFF_Y = 2 };
 int gemm(Ctx* c, int ab_prec, int c_prec, void* const* bufs, const GemmTask* d_tasks, const Sched& sched,
-         const GemmChunk* d_chunks);
+         const GemmChunk* d_chunks, int kind = GK_OTHER);
 int gemm_reduce(Ctx* c, int c_prec, void* const* bufs, const RedTask* d_tasks, int ntasks);
 
 // ------------------------------------------------------- linear combination

@@ -328,8 +328,8 @@ __device__ __forceinline__ int xcd_task(int ntasks) {
 // slice from LDS; a task's epilogue is written when its last slice has been
 // consumed.
 template <class T, class TC, int BK>
-__global__ void __launch_bounds__(NTH, 4) k_gemm(Bufs bufs, const GemmTask* __restrict__ tasks,
-                                              const GemmChunk* __restrict__ chunks, Sched sc) {
+__device__ __forceinline__ void gemm_body(const Bufs& bufs, const GemmTask* __restrict__ tasks,
+                                          const GemmChunk* __restrict__ chunks, const Sched& sc) {
     typedef typename MmaTraits<T>::acc_t acc_t;
     typedef Slice<T, BK> SL;
     constexpr int LDK = SL::LDK;
@@ -501,6 +501,21 @@ __global__ void __launch_bounds__(NTH, 4) k_gemm(Bufs bufs, const GemmTask* __re
     }
 }
 
+// The same body under three names, so that profiles separate the two
+// H_eff phases from the renormalisation and prediction GEMMs.
+template <class T, class TC, int BK>
+__global__ void __launch_bounds__(NTH, 4) k_gemm(Bufs b, const GemmTask* t, const GemmChunk* c, Sched s) {
+    gemm_body<T, TC, BK>(b, t, c, s);
+}
+template <class T, class TC, int BK>
+__global__ void __launch_bounds__(NTH, 4) k_heff_z(Bufs b, const GemmTask* t, const GemmChunk* c, Sched s) {
+    gemm_body<T, TC, BK>(b, t, c, s);
+}
+template <class T, class TC, int BK>
+__global__ void __launch_bounds__(NTH, 4) k_heff_y(Bufs b, const GemmTask* t, const GemmChunk* c, Sched s) {
+    gemm_body<T, TC, BK>(b, t, c, s);
+}
+
 // ---- BF16: K slice 32, one v_mfma_f32_16x16x32_bf16 per 16x16 block and slice
 // LDS holds fp32-converted-to-bf16 values as As[m][k] and Bs[n][k] (k fastest)
 // so that a lane's 8 consecutive k values are one 16-byte read.
@@ -622,16 +637,27 @@ __global__ void __launch_bounds__(NTH) k_gemm_bf16(Bufs bufs, const GemmTask* __
 }
 
 int gemm(Ctx* c, int ab, int cp, void* const* bufs, const GemmTask* tasks, const Sched& sc,
-         const GemmChunk* chunks) {
+         const GemmChunk* chunks, int kind) {
     const int ntasks = sc.ntasks;
     if (ntasks <= 0) return 0;
     Bufs b;
     for (int i = 0; i < kMaxBufs; ++i) b.p[i] = bufs[i];
     dim3 pgrid(std::max(1, sc.nwg)), block(NTH), grid(((ntasks + 7) / 8) * 8);
-    if (ab == P_F64 && cp == P_F64)
-        hipLaunchKernelGGL((k_gemm<double, double, 16>), pgrid, block, 0, c->stream, b, tasks, chunks, sc);
-    else if (ab == P_F32 && cp == P_F32)
-        hipLaunchKernelGGL((k_gemm<float, float, 32>), pgrid, block, 0, c->stream, b, tasks, chunks, sc);
+    if (ab == P_F64 && cp == P_F64) {
+        if (kind == GK_HEFF_Z)
+            hipLaunchKernelGGL((k_heff_z<double, double, 16>), pgrid, block, 0, c->stream, b, tasks, chunks, sc);
+        else if (kind == GK_HEFF_Y)
+            hipLaunchKernelGGL((k_heff_y<double, double, 16>), pgrid, block, 0, c->stream, b, tasks, chunks, sc);
+        else
+            hipLaunchKernelGGL((k_gemm<double, double, 16>), pgrid, block, 0, c->stream, b, tasks, chunks, sc);
+    } else if (ab == P_F32 && cp == P_F32) {
+        if (kind == GK_HEFF_Z)
+            hipLaunchKernelGGL((k_heff_z<float, float, 32>), pgrid, block, 0, c->stream, b, tasks, chunks, sc);
+        else if (kind == GK_HEFF_Y)
+            hipLaunchKernelGGL((k_heff_y<float, float, 32>), pgrid, block, 0, c->stream, b, tasks, chunks, sc);
+        else
+            hipLaunchKernelGGL((k_gemm<float, float, 32>), pgrid, block, 0, c->stream, b, tasks, chunks, sc);
+    }
     else if (ab == P_BF16 && cp == P_F32)
         hipLaunchKernelGGL((k_gemm_bf16<float>), grid, block, 0, c->stream, b, tasks, chunks, ntasks);
     else if (ab == P_BF16 && cp == P_BF16)

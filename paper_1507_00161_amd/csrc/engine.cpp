@@ -209,9 +209,12 @@ struct GB {
     }
 };
 
-dmrg_status Engine::run_gemm(int prec, BufTable bufs, const GemmPlan& p, int cprec) {
-    if (p.ntasks == 0) return DMRG_OK;
+dmrg_status Engine::run_gemm(int prec, BufTable bufs, const GemmPlan& p, int cprec, int kind, int ev_mid) {
     if (cprec < 0) cprec = prec == dmrgdev::P_BF16 ? dmrgdev::P_F32 : prec;
+    if (p.ntasks == 0) {
+        if (ev_mid >= 0) DEV(dmrgdev::event_record(dev_, ev_mid));
+        return DMRG_OK;
+    }
     if (p.nslots) {
         TRY(ensure_partials(p.nslots));
         bufs[dmrgdev::kPartialBuf] = partial_.p;
@@ -221,7 +224,8 @@ dmrg_status Engine::run_gemm(int prec, BufTable bufs, const GemmPlan& p, int cpr
     sc.nwg = p.nwg;
     sc.nfull = p.nfull;
     sc.ntasks = p.ntasks;
-    DEV(dmrgdev::gemm(dev_, prec, cprec, bufs.data(), p.tasks.as<GemmTask>(), sc, p.chunks.as<GemmChunk>()));
+    DEV(dmrgdev::gemm(dev_, prec, cprec, bufs.data(), p.tasks.as<GemmTask>(), sc, p.chunks.as<GemmChunk>(), kind));
+    if (ev_mid >= 0) DEV(dmrgdev::event_record(dev_, ev_mid));
     if (p.nreds)
         DEV(dmrgdev::gemm_reduce(dev_, cprec, bufs.data(), p.reds.as<dmrgdev::RedTask>(), p.nreds));
     return DMRG_OK;
@@ -1533,12 +1537,12 @@ dmrg_status Engine::heff_launch(Bond& B, const double* x, double* y, int prec, b
         for (size_t g = 0; g < B.groups.size(); ++g) {
             BufTable bufs{B.Sops.pool.p, B.Eops.pool.p, (void*)x, z_.p, y};
             if (timed) DEV(dmrgdev::event_record(dev_, 2));
-            TRY(run_gemm(prec, bufs, B.groups[g].p1));
+            TRY(run_gemm(prec, bufs, B.groups[g].p1, -1, dmrgdev::GK_HEFF_Z));
             if (timed) DEV(dmrgdev::event_record(dev_, 3));
-            TRY(run_gemm(prec, bufs, B.groups[g].p2));
+            TRY(run_gemm(prec, bufs, B.groups[g].p2, -1, dmrgdev::GK_HEFF_Y, timed ? 4 : -1));
             if (timed) {
-                DEV(dmrgdev::event_record(dev_, 4));
-                account(B.groups[g], es, es);
+                DEV(dmrgdev::event_record(dev_, 5));
+                if (opt_.precision == DMRG_FP64) account(B.groups[g], es, es);
             }
         }
         return DMRG_OK;
@@ -1555,11 +1559,11 @@ dmrg_status Engine::heff_launch(Bond& B, const double* x, double* y, int prec, b
     for (size_t g = 0; g < B.groups.size(); ++g) {
         BufTable bufs{B.Sops.pool_lo.p, B.Eops.pool_lo.p, xlo_.p, scr_a_.p, ylo_.p};
         if (timed) DEV(dmrgdev::event_record(dev_, 2));
-        TRY(run_gemm(prec, bufs, B.groups[g].p1, prec));          // Z in the operand precision
+        TRY(run_gemm(prec, bufs, B.groups[g].p1, prec, dmrgdev::GK_HEFF_Z));   // Z in the operand precision
         if (timed) DEV(dmrgdev::event_record(dev_, 3));
-        TRY(run_gemm(prec, bufs, B.groups[g].p2, dmrgdev::P_F32));
+        TRY(run_gemm(prec, bufs, B.groups[g].p2, dmrgdev::P_F32, dmrgdev::GK_HEFF_Y, timed ? 4 : -1));
         if (timed) {
-            DEV(dmrgdev::event_record(dev_, 4));
+            DEV(dmrgdev::event_record(dev_, 5));
             account(B.groups[g], es, es);
         }
     }
@@ -1569,6 +1573,7 @@ dmrg_status Engine::heff_launch(Bond& B, const double* x, double* y, int prec, b
 
 void Engine::account(const HeffGroup& g, double es1, double es2) {
     double t1 = dmrgdev::event_elapsed(dev_, 2, 3), t2 = dmrgdev::event_elapsed(dev_, 3, 4);
+    acc_.reduce_seconds += dmrgdev::event_elapsed(dev_, 4, 5);
     if (g.p1.ntasks) {
         acc_.gemm1_launches += 1;
         acc_.gemm1_seconds += t1;

@@ -353,7 +353,9 @@ private:
     dmrg_status density_matrix(Bond& B, bool left, double alpha, Buf& rho,
                                const std::vector<int64_t>& roff, const std::vector<int>& rld);
     dmrg_status random_psi(Bond& B, Buf& out);
-    dmrg_status run_gemm(int prec, BufTable bufs, const GemmPlan& p, int cprec = -1);
+    // ev_mid >= 0: record that event between the GEMM and its split-K reduction
+    dmrg_status run_gemm(int prec, BufTable bufs, const GemmPlan& p, int cprec = -1,
+                         int kind = dmrgdev::GK_OTHER, int ev_mid = -1);
     dmrg_status ensure_partials(int64_t slots);
     Buf partial_;
     dmrg_status ensure_dv(int64_t n, int kmax);
