@@ -242,10 +242,11 @@ dmrg_status Engine::ensure_partials(int64_t slots) {
 // tiles and split-K parts, which are consecutive in `tasks`) are dealt to the
 // 8 XCDs, each onto the least-loaded XCD, so that the tiles sharing A rows
 // or B columns share one L2; blocks larger than 1/64 of the launch are dealt
-// tile by tile.  Within an XCD, each task goes to its least-loaded
-// work-group.  When work-groups get few tasks, both dealings go
-// longest-first.  Tasks without chunks (pure clears) are moved behind all
-// others.  The task vector is reordered in place: work-group
+// tile by tile.  When work-groups get few tasks (under 16 each), units and
+// then tasks go longest-first, each task to its XCD's least-loaded
+// work-group; with more tasks, both dealings keep plan order and tasks go
+// round-robin over the XCD's work-groups (no sorting).  Tasks without chunks
+// (pure clears) are moved behind all others.  The task vector is reordered in place: work-group
 // w = 8 j + x runs [wg_off[w], wg_off[w+1]).
 static void schedule_tasks(const GB& g, std::vector<GemmTask>& tasks, const std::vector<int32_t>& owner,
                            std::vector<int32_t>& wg_off, int& nwg, int& nfull) {
@@ -283,9 +284,6 @@ static void schedule_tasks(const GB& g, std::vector<GemmTask>& tasks, const std:
         }
         t = e;
     }
-    // Longest-first (LPT) dealing pays off when work-groups get few tasks; with
-    // many tasks per work-group, dealing in plan order to the least-loaded
-    // target balances as well and needs no sort.
     const bool lpt = nf < 16 * (int64_t)nwg;
     if (lpt)
         std::sort(units.begin(), units.end(),
@@ -319,24 +317,34 @@ static void schedule_tasks(const GB& g, std::vector<GemmTask>& tasks, const std:
                 if (xcd_of[t] >= 0) order[fp[xcd_of[t]]++] = t;
         }
     }
-    // per XCD: each task onto its least-loaded work-group
+    // per XCD: each task onto its least-loaded work-group (LPT), or, with many
+    // tasks per work-group, round-robin over the work-groups
     std::vector<int32_t> wg_of(n, -1);
-    typedef std::pair<double, int> QE;
-    std::vector<QE> heap;
-    auto cmp = [](const QE& a, const QE& b) { return a > b; };   // min-heap on (load, j)
-    for (int x = 0; x < 8; ++x) {
-        auto b = order.begin() + xoff[x], e = order.begin() + xoff[x + 1];
-        if (lpt)
+    if (lpt) {
+        typedef std::pair<double, int> QE;
+        std::vector<QE> heap;
+        auto cmp = [](const QE& a, const QE& b) { return a > b; };   // min-heap on (load, j)
+        for (int x = 0; x < 8; ++x) {
+            auto b = order.begin() + xoff[x], e = order.begin() + xoff[x + 1];
             std::sort(b, e, [&](int64_t p, int64_t q) { return cost[p] != cost[q] ? cost[p] > cost[q] : p < q; });
-        heap.clear();
-        for (int j = 0; j < gw; ++j) heap.push_back({0.0, j});
-        std::make_heap(heap.begin(), heap.end(), cmp);
-        for (auto it = b; it != e; ++it) {
-            std::pop_heap(heap.begin(), heap.end(), cmp);
-            QE& q = heap.back();
-            wg_of[*it] = 8 * q.second + x;
-            q.first += cost[*it];
-            std::push_heap(heap.begin(), heap.end(), cmp);
+            heap.clear();
+            for (int j = 0; j < gw; ++j) heap.push_back({0.0, j});
+            std::make_heap(heap.begin(), heap.end(), cmp);
+            for (auto it = b; it != e; ++it) {
+                std::pop_heap(heap.begin(), heap.end(), cmp);
+                QE& q = heap.back();
+                wg_of[*it] = 8 * q.second + x;
+                q.first += cost[*it];
+                std::push_heap(heap.begin(), heap.end(), cmp);
+            }
+        }
+    } else {
+        for (int x = 0; x < 8; ++x) {
+            int j = 0;
+            for (int64_t i = xoff[x]; i < xoff[x + 1]; ++i) {
+                wg_of[order[i]] = 8 * j + x;
+                if (++j == gw) j = 0;
+            }
         }
     }
     // counting sort by work-group; within a work-group, tasks keep dealing order
@@ -357,7 +365,8 @@ static dmrg_status finish_plan(Engine& e, GB& g, GemmPlan& p) {
     using dmrgdev::kTileM;
     using dmrgdev::kTileN;
     std::vector<GemmTask> tasks;
-    std::vector<int32_t> owner;   // output block of each task
+    std::vector<int32_t> owner;   // scheduling unit of each task
+    int32_t unit = 0;
     std::vector<dmrgdev::RedTask> reds;
     // total work in K units, tile by tile
     double work = 0.0;
@@ -397,6 +406,10 @@ static dmrg_status finish_plan(Engine& e, GB& g, GemmPlan& p) {
             }
             if (start < ob.ce) ranges.push_back({start, ob.ce});
         }
+        // tiles of the block; with split-K, tasks are listed part by part so
+        // that the tiles reading one chunk range (the same A rows and B
+        // columns) form one scheduling unit
+        std::vector<GemmTask> tiles;
         for (int m0 = 0; m0 < ob.M; m0 += kTileM)
             for (int n0 = 0; n0 < ob.Nn; n0 += kTileN) {
                 GemmTask t{};
@@ -405,40 +418,51 @@ static dmrg_status finish_plan(Engine& e, GB& g, GemmPlan& p) {
                 t.n0 = n0;
                 t.mt = std::min(kTileM, ob.M - m0);
                 t.nt = std::min(kTileN, ob.Nn - n0);
-                if (ranges.size() == 1) {
-                    t.c_off = ob.coff;
-                    t.chunk_begin = (int32_t)ranges[0].first;
-                    t.chunk_end = (int32_t)ranges[0].second;
-                    t.c_buf = (uint8_t)ob.cbuf;
-                    t.beta = (uint8_t)ob.beta;
-                    t.c_local = 0;
-                    tasks.push_back(t);
-                    owner.push_back((int32_t)(&ob - g.obs.data()));
-                    continue;
-                }
-                dmrgdev::RedTask r{};
-                r.dst_off = ob.coff + (int64_t)m0 * ob.ldc + n0;
-                r.ld = ob.ldc;
-                r.mt = t.mt;
-                r.nt = t.nt;
-                r.slot0 = (int32_t)slot;
-                r.nslots = (int32_t)ranges.size();
-                r.dst_buf = (uint8_t)ob.cbuf;
-                r.beta = (uint8_t)ob.beta;
-                reds.push_back(r);
-                for (auto& rg : ranges) {
-                    GemmTask u = t;
-                    u.c_off = slot * (int64_t)kTileM * kTileN;
-                    u.chunk_begin = (int32_t)rg.first;
-                    u.chunk_end = (int32_t)rg.second;
-                    u.c_buf = (uint8_t)dmrgdev::kPartialBuf;
-                    u.beta = 0;
-                    u.c_local = 1;
-                    tasks.push_back(u);
-                    owner.push_back((int32_t)(&ob - g.obs.data()));
-                    ++slot;
-                }
+                tiles.push_back(t);
             }
+        if (ranges.size() == 1) {
+            for (GemmTask t : tiles) {
+                t.c_off = ob.coff;
+                t.chunk_begin = (int32_t)ranges[0].first;
+                t.chunk_end = (int32_t)ranges[0].second;
+                t.c_buf = (uint8_t)ob.cbuf;
+                t.beta = (uint8_t)ob.beta;
+                t.c_local = 0;
+                tasks.push_back(t);
+                owner.push_back(unit);
+            }
+            ++unit;
+            continue;
+        }
+        const int64_t nparts = (int64_t)ranges.size();
+        for (size_t q = 0; q < tiles.size(); ++q) {
+            const GemmTask& t = tiles[q];
+            dmrgdev::RedTask r{};
+            r.dst_off = ob.coff + (int64_t)t.m0 * ob.ldc + t.n0;
+            r.ld = ob.ldc;
+            r.mt = t.mt;
+            r.nt = t.nt;
+            r.slot0 = (int32_t)(slot + (int64_t)q * nparts);
+            r.nslots = (int32_t)nparts;
+            r.dst_buf = (uint8_t)ob.cbuf;
+            r.beta = (uint8_t)ob.beta;
+            reds.push_back(r);
+        }
+        for (int64_t pq = 0; pq < nparts; ++pq) {
+            for (size_t q = 0; q < tiles.size(); ++q) {
+                GemmTask u = tiles[q];
+                u.c_off = (slot + (int64_t)q * nparts + pq) * (int64_t)kTileM * kTileN;
+                u.chunk_begin = (int32_t)ranges[pq].first;
+                u.chunk_end = (int32_t)ranges[pq].second;
+                u.c_buf = (uint8_t)dmrgdev::kPartialBuf;
+                u.beta = 0;
+                u.c_local = 1;
+                tasks.push_back(u);
+                owner.push_back(unit);
+            }
+            ++unit;
+        }
+        slot += (int64_t)tiles.size() * nparts;
     }
     (void)ntiles;
     std::vector<int32_t> wg_off;
