@@ -149,7 +149,11 @@ int syevd(Ctx* c, int n, double* A, double* w);
 // `count` symmetric P x P matrices at stride P*P, solved together (same
 // output convention; w at stride P).
 int syevd_batched(Ctx* c, int P, int count, double* A, double* w);
-int syevj_batched(Ctx* c, int P, int count, double* A, double* w);
+// Buckets j = 0..nb-1 of count[j] padded P[j] x P[j] matrices at A + aoff[j]
+// (eigenvalues at w + woff[j]), solved concurrently; ordered after all prior
+// work of the context stream, and later work waits for them.
+int syevd_buckets(Ctx* c, int nb, const int* P, const int* count, double* A, const int64_t* aoff, double* w,
+                  const int64_t* woff);
 // Prepare padded slots: for slot s (base + s*P*P, real size n[s]) write 0
 // outside the leading n x n block and -1 on the padding diagonal, so the
 // padding eigenpairs are (-1, unit vectors of the padding rows).

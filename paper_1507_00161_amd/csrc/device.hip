@@ -23,6 +23,8 @@
 
 namespace dmrgdev {
 
+constexpr int kSide = 4;
+
 struct Ctx {
     int device = 0;
     hipStream_t stream = nullptr;
@@ -37,6 +39,14 @@ struct Ctx {
     size_t syev_cap = 0;
     int* info = nullptr;
     size_t info_cap = 0;
+    // side streams for concurrent eigensolver buckets (default priority)
+    bool side_ready = false;
+    hipStream_t side[4] = {};
+    rocblas_handle side_blas[4] = {};
+    hipEvent_t side_ev[4] = {}, fork_ev = nullptr;
+    double* side_e[4] = {};
+    int* side_info[4] = {};
+    size_t side_ecap[4] = {}, side_icap[4] = {};
     // pinned staging arena for stream-ordered uploads
     char* stage = nullptr;
     size_t stage_cap = 0, stage_off = 0;
@@ -107,6 +117,17 @@ void ctx_destroy(Ctx* c) {
     if (c->syev_e) hipFree(c->syev_e);
     if (c->info) hipFree(c->info);
     if (c->stage) hipHostFree(c->stage);
+    if (c->side_ready) {
+        for (int i = 0; i < kSide; ++i) {
+            hipStreamSynchronize(c->side[i]);
+            rocblas_destroy_handle(c->side_blas[i]);
+            hipEventDestroy(c->side_ev[i]);
+            hipStreamDestroy(c->side[i]);
+            if (c->side_e[i]) hipFree(c->side_e[i]);
+            if (c->side_info[i]) hipFree(c->side_info[i]);
+        }
+        hipEventDestroy(c->fork_ev);
+    }
     if (c->own_stream) hipStreamDestroy(c->stream);
     delete c;
 }
@@ -1109,31 +1130,81 @@ int syevd_batched(Ctx* c, int P, int count, double* A, double* w) {
     return 0;
 }
 
-// Jacobi variant of the batched solver (same layout and output order).
-int syevj_batched(Ctx* c, int P, int count, double* A, double* w) {
-    if (count <= 0 || P <= 0) return 0;
-    size_t need = (size_t)2 * count;   // residuals + sweep counts
-    if (c->syev_cap < need) {
-        if (c->syev_e) hipFree(c->syev_e);
-        c->syev_e = nullptr;
-        c->syev_cap = 0;
-        HIPCHK(c, hipMalloc(&c->syev_e, need * sizeof(double)));
-        c->syev_cap = need;
+// Several size buckets at once.  The rocSOLVER divide-and-conquer solver is a
+// long chain of small launches per bucket, so the buckets run concurrently on
+// side streams (longest chain first onto the least-loaded stream), each after
+// all earlier work of the context stream; the context stream then waits for
+// all of them.
+int syevd_buckets(Ctx* c, int nb, const int* P, const int* count, double* A, const int64_t* aoff, double* w,
+                  const int64_t* woff) {
+    if (nb <= 0) return 0;
+    if (!c->side_ready) {
+        for (int i = 0; i < kSide; ++i) {
+            HIPCHK(c, hipStreamCreateWithFlags(&c->side[i], hipStreamNonBlocking));
+            if (rocblas_create_handle(&c->side_blas[i]) != rocblas_status_success) {
+                c->err = "rocblas_create_handle failed";
+                return 1;
+            }
+            rocblas_set_stream(c->side_blas[i], c->side[i]);
+            HIPCHK(c, hipEventCreateWithFlags(&c->side_ev[i], hipEventDisableTiming));
+        }
+        HIPCHK(c, hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming));
+        c->side_ready = true;
     }
-    if (c->info_cap < (size_t)count) {
-        if (c->info) hipFree(c->info);
-        c->info = nullptr;
-        c->info_cap = 0;
-        HIPCHK(c, hipMalloc(&c->info, (size_t)count * sizeof(int)));
-        c->info_cap = count;
+    // longest chains first onto the least-loaded side stream
+    std::vector<int> ord(nb), sid(nb);
+    for (int j = 0; j < nb; ++j) ord[j] = j;
+    std::sort(ord.begin(), ord.end(), [&](int a, int b) { return P[a] > P[b]; });
+    int64_t load[kSide] = {0, 0, 0, 0};
+    size_t need_e[kSide] = {0, 0, 0, 0}, need_i[kSide] = {0, 0, 0, 0};
+    for (int j : ord) {
+        if (count[j] <= 0 || P[j] <= 0) {
+            sid[j] = -1;
+            continue;
+        }
+        int best = 0;
+        for (int i = 1; i < kSide; ++i)
+            if (load[i] < load[best]) best = i;
+        sid[j] = best;
+        load[best] += P[j];
+        need_e[best] = std::max(need_e[best], (size_t)P[j] * count[j]);
+        need_i[best] = std::max(need_i[best], (size_t)count[j]);
     }
-    rocblas_status st = rocsolver_dsyevj_strided_batched(
-        c->blas, rocblas_esort_ascending, rocblas_evect_original, rocblas_fill_upper, P, A, P, (rocblas_stride)P * P,
-        0.0, c->syev_e, 100, (rocblas_int*)(c->syev_e + count), w, P, c->info, count);
-    if (st != rocblas_status_success) {
-        c->err = std::string("rocsolver_dsyevj_strided_batched failed: ") + rocblas_status_to_string(st);
-        return 1;
+    for (int i = 0; i < kSide; ++i) {
+        if (c->side_ecap[i] < need_e[i]) {
+            if (c->side_e[i]) HIPCHK(c, hipFree(c->side_e[i]));
+            c->side_e[i] = nullptr;
+            c->side_ecap[i] = 0;
+            HIPCHK(c, hipMalloc(&c->side_e[i], need_e[i] * sizeof(double)));
+            c->side_ecap[i] = need_e[i];
+        }
+        if (c->side_icap[i] < need_i[i]) {
+            if (c->side_info[i]) HIPCHK(c, hipFree(c->side_info[i]));
+            c->side_info[i] = nullptr;
+            c->side_icap[i] = 0;
+            HIPCHK(c, hipMalloc(&c->side_info[i], need_i[i] * sizeof(int)));
+            c->side_icap[i] = need_i[i];
+        }
     }
+    HIPCHK(c, hipEventRecord(c->fork_ev, c->stream));
+    for (int i = 0; i < kSide; ++i)
+        if (load[i]) HIPCHK(c, hipStreamWaitEvent(c->side[i], c->fork_ev, 0));
+    for (int j : ord) {
+        const int i = sid[j];
+        if (i < 0) continue;
+        rocblas_status st = rocsolver_dsyevd_strided_batched(
+            c->side_blas[i], rocblas_evect_original, rocblas_fill_upper, P[j], A + aoff[j], P[j],
+            (rocblas_stride)P[j] * P[j], w + woff[j], P[j], c->side_e[i], P[j], c->side_info[i], count[j]);
+        if (st != rocblas_status_success) {
+            c->err = std::string("rocsolver_dsyevd_strided_batched failed: ") + rocblas_status_to_string(st);
+            return 1;
+        }
+    }
+    for (int i = 0; i < kSide; ++i)
+        if (load[i]) {
+            HIPCHK(c, hipEventRecord(c->side_ev[i], c->side[i]));
+            HIPCHK(c, hipStreamWaitEvent(c->stream, c->side_ev[i], 0));
+        }
     return 0;
 }
 

@@ -2103,8 +2103,18 @@ dmrg_status Engine::truncate_and_move(int D, double alpha, double* disc) {
         TRY(density_matrix(B, left, alpha, rho, roff, rld));
         acc_.density_seconds += now() - td;
         td = now();
-        for (auto& b4 : bk)
-            DEV(dmrgdev::syevd_batched(dev_, (int)b4[0], (int)b4[1], rho.d() + b4[2], w.d() + b4[3]));
+        {
+            std::vector<int> bP, bc;
+            std::vector<int64_t> ba, bw;
+            for (auto& b4 : bk) {
+                bP.push_back((int)b4[0]);
+                bc.push_back((int)b4[1]);
+                ba.push_back(b4[2]);
+                bw.push_back(b4[3]);
+            }
+            DEV(dmrgdev::syevd_buckets(dev_, (int)bk.size(), bP.data(), bc.data(), rho.d(), ba.data(), w.d(),
+                                       bw.data()));
+        }
         std::vector<double> hwall(wtot);
         DEV(dmrgdev::d2h(dev_, hwall.data(), w.p, wtot * sizeof(double)));
         // compact the real eigenvalues: block x owns hw[woff[x] .. woff[x] + rdim[x])
