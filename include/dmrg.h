@@ -73,8 +73,12 @@ typedef struct dmrg_sweep_stats {
     double heff_flops;        /* algorithmic flops of all H_eff.psi products */
     double heff_seconds;      /* device time of all H_eff.psi products (HIP events) */
     double sweep_seconds;     /* wall time of the sweep */
-    double renorm_seconds;    /* wall time in truncation + renormalisation + prediction */
-    double blocking_seconds;  /* wall time building enlarged-block operators and plans */
+    /* Host wall time of the stages below.  Device work is queued without
+     * waiting where nothing on the host needs its result, so a stage's time
+     * includes device work only up to the waits it makes (the eigenvalue read
+     * of the truncation, the norm check of the prediction). */
+    double renorm_seconds;    /* truncation + renormalisation + prediction (incl. blocking) */
+    double blocking_seconds;  /* building enlarged-block operators and plans */
     double density_seconds;   /* of renorm_seconds: reduced density matrices */
     double eig_seconds;       /* of renorm_seconds: sector eigendecompositions + selection */
     double renormalize_seconds; /* of renorm_seconds: U^T O U of the kept operators */

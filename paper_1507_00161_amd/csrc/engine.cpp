@@ -515,8 +515,8 @@ struct LB {
         if (st) return st;
         if (dmrgdev::lincomb(e.dev(), bufs, dt.as<LcTask>(), (int)tasks.size(), dterm.as<LcTerm>()))
             return e.fail(DMRG_ERR_DEVICE, dmrgdev::last_error(e.dev()));
-        // the task lists are freed on return: wait for the kernel
-        if (dmrgdev::sync(e.dev())) return e.fail(DMRG_ERR_DEVICE, dmrgdev::last_error(e.dev()));
+        // the task lists go back to the stream-ordered cache on return: later
+        // users are ordered after this kernel, so no wait is needed
         return DMRG_OK;
     }
 };
@@ -1152,7 +1152,6 @@ dmrg_status Engine::renormalize(const Enl& en, const OpSet& ops, bool normal_in,
     BufTable bufs{ops.pool.p, out.iso.p, tbuf.p, out.ops.pool.p, tmp.pool.p};
     TRY(run_gemm(dmrgdev::P_F64, bufs, p1));
     TRY(run_gemm(dmrgdev::P_F64, bufs, p2));
-    DEV(dmrgdev::sync(dev_));
     if (!transition) return DMRG_OK;
     // complementary operators of the new block from its renormalised normal ones
     FormulaCtx F{*this, out};
@@ -1528,7 +1527,6 @@ dmrg_status Engine::build_diag(Bond& B) {
     TRY(upload(dterm, terms));
     double* bufs[3] = {B.Sops.pool.d(), B.Eops.pool.d(), B.diag.d()};
     if (!tasks.empty()) DEV(dmrgdev::diag(dev_, bufs, dt.as<DiagTask>(), (int)tasks.size(), dterm.as<DiagTerm>()));
-    DEV(dmrgdev::sync(dev_));
     return DMRG_OK;
 }
 
@@ -2006,7 +2004,6 @@ dmrg_status Engine::density_matrix(Bond& B, bool left, double alpha, Buf& rho, c
     BufTable bufs{psi_.p, ops.pool.p, phib.p, rho.p};
     TRY(run_gemm(dmrgdev::P_F64, bufs, p1));
     TRY(run_gemm(dmrgdev::P_F64, bufs, p2));
-    DEV(dmrgdev::sync(dev_));
     return DMRG_OK;
 }
 
@@ -2174,7 +2171,6 @@ dmrg_status Engine::truncate_and_move(int D, double alpha, double* disc) {
             DEV(dmrgdev::gather_evecs(dev_, rho.d() + roff[x], rdim[x], rld[x], idxb.as<int32_t>() + jobs[y][1],
                                       (int)jobs[y][2], blk->iso.d() + iso_off[y]));
         }
-        DEV(dmrgdev::sync(dev_));
         acc_.eig_seconds += now() - td;
     }
     for (size_t y = 0; y < keep_m.size(); ++y) {
