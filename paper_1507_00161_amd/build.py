@@ -19,7 +19,7 @@ ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 
 HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-Wall",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
-HOST_FLAGS = ["-O2", "-fPIC", "-std=c++17", "-Wall"]
+HOST_FLAGS = ["-O2", "-fPIC", "-std=c++17", "-Wall", "-pthread"]
 
 
 def _run(cmd):
@@ -44,7 +44,7 @@ def build(verbose: bool = False) -> str:
         objs.append(obj)
     tmp = OUT + ".tmp"
     _run([hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp,
-          f"-L{ROCM}/lib", "-lrocsolver", "-lrocblas", f"-Wl,-rpath,{ROCM}/lib"])
+          f"-L{ROCM}/lib", "-lrocsolver", "-lrocblas", "-lpthread", f"-Wl,-rpath,{ROCM}/lib"])
     os.replace(tmp, OUT)
     if verbose:
         print("built", OUT)

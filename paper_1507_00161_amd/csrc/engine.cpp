@@ -23,6 +23,7 @@
 #include <queue>
 #include <set>
 #include <sstream>
+#include <thread>
 
 namespace dm {
 
@@ -361,13 +362,20 @@ static void schedule_tasks(const GB& g, std::vector<GemmTask>& tasks, const std:
     tasks.swap(out);
 }
 
-static dmrg_status finish_plan(Engine& e, GB& g, GemmPlan& p) {
+// Host part of a plan: tiles, split-K parts and the schedule (no device
+// calls, so two plans can be prepared on two threads).
+struct PlanHost {
+    std::vector<GemmTask> tasks;
+    std::vector<dmrgdev::RedTask> reds;
+    std::vector<int32_t> wg_off;
+};
+static void plan_host(const GB& g, GemmPlan& p, PlanHost& h) {
     using dmrgdev::kTileM;
     using dmrgdev::kTileN;
-    std::vector<GemmTask> tasks;
+    std::vector<GemmTask>& tasks = h.tasks;
     std::vector<int32_t> owner;   // scheduling unit of each task
     int32_t unit = 0;
-    std::vector<dmrgdev::RedTask> reds;
+    std::vector<dmrgdev::RedTask>& reds = h.reds;
     // total work in K units, tile by tile
     double work = 0.0;
     int64_t ntiles = 0;
@@ -465,21 +473,40 @@ static dmrg_status finish_plan(Engine& e, GB& g, GemmPlan& p) {
         slot += (int64_t)tiles.size() * nparts;
     }
     (void)ntiles;
-    std::vector<int32_t> wg_off;
-    schedule_tasks(g, tasks, owner, wg_off, p.nwg, p.nfull);
+    schedule_tasks(g, tasks, owner, h.wg_off, p.nwg, p.nfull);
     p.ntasks = (int)tasks.size();
     p.nreds = (int)reds.size();
     p.nslots = slot;
     p.nchunks = (int64_t)g.chunks.size();
     p.flops = g.flops;
     p.elems = g.elems;
-    dmrg_status st = e.upload(p.tasks, tasks);
+}
+
+static dmrg_status plan_upload(Engine& e, const GB& g, GemmPlan& p, const PlanHost& h) {
+    dmrg_status st = e.upload(p.tasks, h.tasks);
     if (st) return st;
-    st = e.upload(p.wg_off, wg_off);
+    st = e.upload(p.wg_off, h.wg_off);
     if (st) return st;
-    st = e.upload(p.reds, reds);
+    st = e.upload(p.reds, h.reds);
     if (st) return st;
     return e.upload(p.chunks, g.chunks);
+}
+
+static dmrg_status finish_plan(Engine& e, GB& g, GemmPlan& p) {
+    PlanHost h;
+    plan_host(g, p, h);
+    return plan_upload(e, g, p, h);
+}
+
+// Both plans of one H_eff term group: the host parts on two threads.
+static dmrg_status finish_plans(Engine& e, GB& g1, GemmPlan& p1, GB& g2, GemmPlan& p2) {
+    PlanHost h1, h2;
+    std::thread t([&] { plan_host(g1, p1, h1); });
+    plan_host(g2, p2, h2);
+    t.join();
+    dmrg_status st = plan_upload(e, g1, p1, h1);
+    if (st) return st;
+    return plan_upload(e, g2, p2, h2);
 }
 
 // ------------------------------------------------ linear-combination builder
@@ -962,6 +989,17 @@ static std::vector<std::pair<Key, Formula>> right_formulas(const Engine& e, cons
 // its operators from the formulas, executed as scaled block copies.
 dmrg_status Engine::enlarge(const Stored& base, char side, const std::vector<QN>& allowed, Enl& en,
                             OpSet& ops) {
+    LB lb;
+    std::string why;
+    if (!enlarge_plan(base, side, allowed, en, ops, lb, why)) return fail(DMRG_ERR_DEVICE, why);
+    return enlarge_run(base, ops, lb);
+}
+
+// Host part of `enlarge`: no device calls and no change to the engine, so the
+// two blocks of a bond can be planned on two threads.  Returns false (with a
+// message) on an internal inconsistency.
+bool Engine::enlarge_plan(const Stored& base, char side, const std::vector<QN>& allowed, Enl& en, OpSet& ops,
+                          LB& lb, std::string& why) const {
     const int s = side == 'L' ? base.hi : base.lo - 1;
     en = Enl();
     en.side = side;
@@ -998,7 +1036,6 @@ dmrg_status Engine::enlarge(const Stored& base, char side, const std::vector<QN>
     // operators
     auto formulas = side == 'L' ? left_formulas(*this, base) : right_formulas(*this, base);
     ops = OpSet();
-    LB lb;
     for (auto& kf : formulas) {
         const Formula& f = kf.second;
         if (f.empty()) continue;
@@ -1060,7 +1097,10 @@ dmrg_status Engine::enlarge(const Stored& base, char side, const std::vector<QN>
         for (auto& c : contrib) {
             const Sub& so = en.sub[c.first.first];
             const Sub& si = en.sub[c.first.second];
-            if (so.q != si.q + dq) return fail(DMRG_ERR_DEVICE, "internal: inconsistent blocking formula");
+            if (so.q != si.q + dq) {
+                why = "internal: inconsistent blocking formula";
+                return false;
+            }
             Blk bk{c.first.first, c.first.second, ops.alloc_block(so.dim, si.dim), so.dim, si.dim};
             op.blk.push_back(bk);
             lb.block(1, bk.off, bk.rows, bk.cols, c.second);
@@ -1068,6 +1108,11 @@ dmrg_status Engine::enlarge(const Stored& base, char side, const std::vector<QN>
         op.index();
         ops.add(kf.first, std::move(op));
     }
+    return true;
+}
+
+// Device part of `enlarge`: the operator pool and the block copies.
+dmrg_status Engine::enlarge_run(const Stored& base, OpSet& ops, LB& lb) {
     TRY(alloc_buf(ops.pool, std::max<int64_t>(ops.size, 1) * sizeof(double)));
     double* bufs[2] = {base.ops.pool.d(), ops.pool.d()};
     TRY(lb.run(*this, bufs));
@@ -1289,8 +1334,19 @@ dmrg_status Engine::setup_bond(int b, std::unique_ptr<Bond>& outp) {
             if (ss.count(T_ - q)) eq2.push_back(q);
         eq.swap(eq2);
     }
-    TRY(enlarge(L, 'L', sq, B->S, B->Sops));
-    TRY(enlarge(R, 'R', eq, B->E, B->Eops));
+    // plan the two enlarged blocks on two host threads, then queue their copies
+    {
+        LB lbL, lbR;
+        std::string whyL, whyR;
+        bool okL = false, okR = false;
+        std::thread tl([&] { okL = enlarge_plan(L, 'L', sq, B->S, B->Sops, lbL, whyL); });
+        okR = enlarge_plan(R, 'R', eq, B->E, B->Eops, lbR, whyR);
+        tl.join();
+        if (!okL) return fail(DMRG_ERR_DEVICE, whyL);
+        if (!okR) return fail(DMRG_ERR_DEVICE, whyR);
+        TRY(enlarge_run(L, B->Sops, lbL));
+        TRY(enlarge_run(R, B->Eops, lbR));
+    }
     // psi layout: merged S sectors in order
     B->blk_of_S.assign(B->S.mq.size(), -1);
     for (size_t m = 0; m < B->S.mq.size(); ++m) {
@@ -1435,8 +1491,7 @@ dmrg_status Engine::build_heff_plan(Bond& B) {
             g2.end(4, yoff, ldy, S.sub[o.i].dim, E.sub[o.j].dim, first ? 0 : 1);
             l.clear();
         }
-        TRY(finish_plan(*this, g1, grp.p1));
-        TRY(finish_plan(*this, g2, grp.p2));
+        TRY(finish_plans(*this, g1, grp.p1, g2, grp.p2));
         B.flops += grp.p1.flops + grp.p2.flops;
         B.groups.push_back(std::move(grp));
         g1 = GB();

@@ -243,6 +243,8 @@ struct Bond {
     int lo_prec = -1;
 };
 
+struct LB;   // linear-combination task builder (engine.cpp)
+
 class Engine {
 public:
     Engine(dmrgdev::Ctx* dev, const dmrg_options& opt) : dev_(dev), opt_(opt) {}
@@ -337,6 +339,9 @@ private:
     dmrg_status set_order(const int32_t* ordering);
     dmrg_status initialize(int D);
     std::unique_ptr<Stored> vacuum(char side, int lo);
+    bool enlarge_plan(const Stored& base, char side, const std::vector<QN>& allowed, Enl& en, OpSet& ops,
+                      LB& lb, std::string& why) const;
+    dmrg_status enlarge_run(const Stored& base, OpSet& ops, LB& lb);
     dmrg_status enlarge(const Stored& base, char side, const std::vector<QN>& allowed,
                         Enl& en, OpSet& ops);
     dmrg_status renormalize(const Enl& en, const OpSet& ops, bool normal_in, Stored& out,
