@@ -711,12 +711,14 @@ enum SiteOp { S_I = 0, S_CD = 1, S_C = 2, S_N = 3 };
 static int site_par(int s) { return (s == S_CD || s == S_C) ? 1 : 0; }
 static int site_dsig(int s) { return s == S_CD ? 1 : (s == S_C ? -1 : 0); }
 // nonzero (sigma_out, sigma_in) elements with value 1
-static std::vector<std::pair<int, int>> site_elems(int s) {
+static const std::vector<std::pair<int, int>>& site_elems(int s) {
+    static const std::vector<std::pair<int, int>> e_i = {{0, 0}, {1, 1}}, e_cd = {{1, 0}}, e_c = {{0, 1}},
+                                                   e_n = {{1, 1}};
     switch (s) {
-        case S_I: return {{0, 0}, {1, 1}};
-        case S_CD: return {{1, 0}};
-        case S_C: return {{0, 1}};
-        default: return {{1, 1}};
+        case S_I: return e_i;
+        case S_CD: return e_cd;
+        case S_C: return e_c;
+        default: return e_n;
     }
 }
 struct Ref {
@@ -1028,6 +1030,8 @@ bool Engine::enlarge_plan(const Stored& base, char side, const std::vector<QN>& 
             off += sb.dim;
             ms[sg] = (int)en.sub.size();
             en.sub_of[{b, sg}] = (int)en.sub.size();
+            if (en.sub_tab.size() < (size_t)(2 * b + 2)) en.sub_tab.resize(2 * b + 2, -1);
+            en.sub_tab[2 * b + sg] = (int)en.sub.size();
             en.sub.push_back(sb);
         }
         en.md.push_back(off);
@@ -1036,6 +1040,10 @@ bool Engine::enlarge_plan(const Stored& base, char side, const std::vector<QN>& 
     // operators
     auto formulas = side == 'L' ? left_formulas(*this, base) : right_formulas(*this, base);
     ops = OpSet();
+    const int nbase = (int)base.basis.q.size();
+    const int64_t nsub = (int64_t)en.sub.size();
+    std::vector<std::pair<int64_t, LcTerm>> contrib;
+    std::vector<LcTerm> terms;
     for (auto& kf : formulas) {
         const Formula& f = kf.second;
         if (f.empty()) continue;
@@ -1051,59 +1059,72 @@ bool Engine::enlarge_plan(const Stored& base, char side, const std::vector<QN>& 
         int ds = site_dsig(t0.site);
         QN dq = ds == 1 ? bdq + delta_[s] : (ds == -1 ? bdq - delta_[s] : bdq);
         int par = (bpar + site_par(t0.site)) % 2;
-        // contributions per (out sub, in sub)
-        std::map<std::pair<int, int>, std::vector<LcTerm>> contrib;
+        // contributions (out sub, in sub, term), walking each referenced
+        // operator's blocks (a stored operator has at most one block per input
+        // sector); grouped by (out, in) with a stable sort, which keeps the
+        // term order of the formula inside a group
+        contrib.clear();
         for (const FTerm& t : f) {
-            int tpar = 0;
-            if (!t.ident) tpar = base.ops.ops[t.refs[0].op].par;
-            for (size_t i_in = 0; i_in < en.sub.size(); ++i_in) {
-                const Sub& si = en.sub[i_in];
-                for (auto el : site_elems(t.site)) {
-                    if (el.second != si.sigma) continue;
-                    double sign;
-                    if (side == 'L') sign = (site_par(t.site) && (base.basis.q[si.base].n() & 1)) ? -1.0 : 1.0;
-                    else sign = (tpar && si.sigma) ? -1.0 : 1.0;
-                    if (t.ident) {
-                        int i_out = en.find_sub(si.base, el.first);
-                        if (i_out < 0) continue;
+            const int tpar = t.ident ? 0 : base.ops.ops[t.refs[0].op].par;
+            const auto& els = site_elems(t.site);
+            auto sign_of = [&](int b_in, int sigma) {
+                if (side == 'L') return (site_par(t.site) && (base.basis.q[b_in].n() & 1)) ? -1.0 : 1.0;
+                return (tpar && sigma) ? -1.0 : 1.0;
+            };
+            if (t.ident) {
+                for (int b_in = 0; b_in < nbase; ++b_in)
+                    for (const auto& el : els) {
+                        const int i_in = en.find_sub(b_in, el.second), i_out = en.find_sub(b_in, el.first);
+                        if (i_in < 0 || i_out < 0) continue;
                         LcTerm lt{};
-                        lt.coef = t.icoef * sign;
+                        lt.coef = t.icoef * sign_of(b_in, el.second);
                         lt.ident = 1;
-                        contrib[{i_out, (int)i_in}].push_back(lt);
-                        continue;
+                        contrib.push_back({(int64_t)i_out * nsub + i_in, lt});
                     }
-                    for (const Ref& r : t.refs) {
-                        const Op& o = base.ops.ops[r.op];
-                        const Blk* bk = r.trans ? o.out_blk(si.base) : o.in_blk(si.base);
-                        if (!bk) continue;
-                        int b_out = r.trans ? bk->in : bk->out;
-                        int i_out = en.find_sub(b_out, el.first);
-                        if (i_out < 0) continue;
+                continue;
+            }
+            for (const Ref& r : t.refs) {
+                const Op& o = base.ops.ops[r.op];
+                for (const Blk& bk : o.blk) {
+                    const int b_in = r.trans ? bk.out : bk.in;
+                    const int b_out = r.trans ? bk.in : bk.out;
+                    for (const auto& el : els) {
+                        const int i_in = en.find_sub(b_in, el.second), i_out = en.find_sub(b_out, el.first);
+                        if (i_in < 0 || i_out < 0) continue;
                         LcTerm lt{};
-                        lt.coef = r.coef * sign;
-                        lt.src_off = bk->off;
-                        lt.ld = bk->cols;
+                        lt.coef = r.coef * sign_of(b_in, el.second);
+                        lt.src_off = bk.off;
+                        lt.ld = bk.cols;
                         lt.trans = r.trans;
                         lt.buf = 0;
-                        contrib[{i_out, (int)i_in}].push_back(lt);
+                        contrib.push_back({(int64_t)i_out * nsub + i_in, lt});
                     }
                 }
             }
         }
         if (contrib.empty()) continue;
+        std::stable_sort(contrib.begin(), contrib.end(),
+                         [](const std::pair<int64_t, LcTerm>& x, const std::pair<int64_t, LcTerm>& y) {
+                             return x.first < y.first;
+                         });
         Op op;
         op.dq = dq;
         op.par = par;
-        for (auto& c : contrib) {
-            const Sub& so = en.sub[c.first.first];
-            const Sub& si = en.sub[c.first.second];
+        for (size_t g0 = 0; g0 < contrib.size();) {
+            size_t g1 = g0;
+            terms.clear();
+            while (g1 < contrib.size() && contrib[g1].first == contrib[g0].first) terms.push_back(contrib[g1++].second);
+            const int i_out = (int)(contrib[g0].first / nsub), i_in = (int)(contrib[g0].first % nsub);
+            const Sub& so = en.sub[i_out];
+            const Sub& si = en.sub[i_in];
             if (so.q != si.q + dq) {
                 why = "internal: inconsistent blocking formula";
                 return false;
             }
-            Blk bk{c.first.first, c.first.second, ops.alloc_block(so.dim, si.dim), so.dim, si.dim};
+            Blk bk{i_out, i_in, ops.alloc_block(so.dim, si.dim), so.dim, si.dim};
             op.blk.push_back(bk);
-            lb.block(1, bk.off, bk.rows, bk.cols, c.second);
+            lb.block(1, bk.off, bk.rows, bk.cols, terms);
+            g0 = g1;
         }
         op.index();
         ops.add(kf.first, std::move(op));

@@ -97,14 +97,15 @@ struct Enl {
     std::vector<Sub> sub;
     std::vector<std::array<int, 2>> msub;       // merged -> sub index per sigma (-1: absent)
     std::map<std::pair<int, int>, int> sub_of;  // (base sector, sigma) -> sub index
+    std::vector<int> sub_tab;                   // the same as a table at 2 base + sigma
     std::map<QN, int> midx;
     int find_m(const QN& x) const {
         auto it = midx.find(x);
         return it == midx.end() ? -1 : it->second;
     }
     int find_sub(int base, int sigma) const {
-        auto it = sub_of.find({base, sigma});
-        return it == sub_of.end() ? -1 : it->second;
+        const size_t i = 2 * (size_t)base + sigma;
+        return base >= 0 && i < sub_tab.size() ? sub_tab[i] : -1;
     }
 };
 
