@@ -217,6 +217,47 @@ def copy_reference(mib):
     print(json.dumps({"copied_bytes": a.numel() * 4}))
 
 
+def batched(k: int, precision: str = "fp32"):
+    """Independent small solves: the first k seeded instances (p / sd / pf
+    spaces, 2..8 particles per species, D from 64..512), one sweep each at
+    their D, first one at a time, then all together with dmrg_sweep_many
+    (fresh contexts, same inputs)."""
+    import paper_1507_00161_amd as pk
+    import torch
+    from workloads import batched_instances
+    ws = batched_instances(k)
+
+    def make(w):
+        h = w.hamiltonian()
+        sp = h.space
+        c = pk.Context(precision=PREC[precision], davidson_tol=1e-7, noise=1e-4, noise_sweeps=1, seed=1507)
+        c.load_hamiltonian(sp.species, sp.two_m, h.eps, h.V.ravel(), h.n_p, h.n_n, h.two_M)
+        return c
+
+    ctxs = [make(w) for w in ws]
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    e_seq = [c.sweep(w.D_schedule[0])["energy"] for c, w in zip(ctxs, ws)]
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t
+    for c in ctxs:
+        c.close()
+    ctxs = [make(w) for w in ws]
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    st, out = pk.sweep_many(ctxs, [w.D_schedule[0] for w in ws])
+    torch.cuda.synchronize()
+    t_con = time.perf_counter() - t
+    for c in ctxs:
+        c.close()
+    diff = max(abs(o["energy"] - e) / abs(e) for o, e in zip(out, e_seq))
+    res = {"batched": {"instances": k, "precision": precision, "status": st,
+                       "sequential_s": t_seq, "concurrent_s": t_con, "speedup": t_seq / t_con,
+                       "max_rel_energy_diff": diff,
+                       "spaces": [w.space for w in ws], "D": [w.D_schedule[0] for w in ws]}}
+    print(json.dumps(res))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -232,6 +273,8 @@ def main():
     ap.add_argument("--bench-json", help="the benchmark line of the profiled run")
     ap.add_argument("--kernel", default="k_heff_y<float, float, 32>")
     ap.add_argument("--copy-reference", type=int, metavar="MIB", help="one plain device copy of MIB MiB")
+    ap.add_argument("--batched", type=int, metavar="K",
+                    help="independent small solves: K instances one at a time vs dmrg_sweep_many")
     args = ap.parse_args()
     if args.summarize_trace:
         summarize_trace(args.summarize_trace, args.bench_json, args.kernel)
@@ -241,6 +284,9 @@ def main():
         return
     if args.copy_reference:
         copy_reference(args.copy_reference)
+        return
+    if args.batched:
+        batched(args.batched)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs one GPU; the multi-GPU path (term-sharded H_eff with an "

@@ -163,9 +163,13 @@ dmrg_status dmrg_get_psi(dmrg_ctx* ctx, double* psi_host);
  * prod_{a in mask, ascending} c+_{ordering[a]} |0>.  DMRG_ERR_STATE otherwise. */
 dmrg_status dmrg_heff_configs(dmrg_ctx* ctx, uint64_t* configs);
 
-/* Advance n contexts (same device) by one sweep each with their own ordering
- * (orderings[i] may be NULL) and D[i].  Per-context status in out[i].status;
- * returns the first error, else the largest warning. */
+/* Advance n distinct contexts by one sweep each with their own ordering
+ * (orderings[i] may be NULL) and D[i].  The sweeps are driven from up to 8
+ * host threads, one context per thread at a time; each context keeps its own
+ * stream, so small solves overlap on the device and every result equals that
+ * of a separate dmrg_sweep.  Per-context status in out[i].status (out may be
+ * NULL); returns the first error in context order, else the largest warning.
+ * A NULL or repeated context -> DMRG_ERR_ARG before any work. */
 dmrg_status dmrg_sweep_many(dmrg_ctx** ctxs, int32_t n, const int32_t* const* orderings,
                             const int32_t* D, dmrg_sweep_stats* out);
 

@@ -1,9 +1,13 @@
 // capi.cpp - extern "C" entry points of include/dmrg.h.  Argument checks,
 // exception containment and status translation; the work is in engine.cpp.
+#include <algorithm>
+#include <atomic>
 #include <cstring>
 #include <exception>
 #include <new>
 #include <string>
+#include <thread>
+#include <vector>
 
 #include "../../include/dmrg.h"
 #include "device.h"
@@ -133,12 +137,36 @@ dmrg_status dmrg_heff_configs(dmrg_ctx* c, uint64_t* configs) {
 dmrg_status dmrg_sweep_many(dmrg_ctx** ctxs, int32_t n, const int32_t* const* orderings, const int32_t* D,
                             dmrg_sweep_stats* out) {
     if (!ctxs || n < 0 || !D) return DMRG_ERR_ARG;
+    for (int32_t i = 0; i < n; ++i) {
+        if (!ctxs[i]) return DMRG_ERR_ARG;
+        for (int32_t j = 0; j < i; ++j)
+            if (ctxs[j] == ctxs[i]) return DMRG_ERR_ARG;   // a context runs on one thread at a time
+    }
+    // Each context has its own stream, so sweeps driven from several host
+    // threads overlap on the device: small solves that cannot fill the GPU
+    // alone run side by side.  Every context's work stays in its own order,
+    // so results equal one-at-a-time sweeps.
+    std::vector<dmrg_status> st(n, DMRG_OK);
+    std::vector<dmrg_sweep_stats> res(n);
+    std::atomic<int32_t> next(0);
+    auto worker = [&] {
+        for (int32_t i = next++; i < n; i = next++) {
+            dmrgdev::bind(ctxs[i]->dev);
+            dmrg_sweep_stats s{};
+            st[i] = dmrg_sweep(ctxs[i], orderings ? orderings[i] : nullptr, D[i], &s);
+            s.status = st[i];
+            res[i] = s;
+        }
+    };
+    const int nt = (int)std::min<int32_t>(n, 8);
+    std::vector<std::thread> pool;
+    for (int t = 1; t < nt; ++t) pool.emplace_back(worker);
+    worker();
+    for (auto& t : pool) t.join();
     dmrg_status worst = DMRG_OK;
     for (int32_t i = 0; i < n; ++i) {
-        dmrg_sweep_stats st{};
-        dmrg_status s = dmrg_sweep(ctxs[i], orderings ? orderings[i] : nullptr, D[i], &st);
-        st.status = s;
-        if (out) out[i] = st;
+        if (out) out[i] = res[i];
+        const dmrg_status s = st[i];
         if (s < 0 && worst >= 0) worst = s;
         else if (s > worst && worst >= 0) worst = s;
     }

@@ -30,6 +30,8 @@ int d2h(Ctx* c, void* dst, const void* src, size_t bytes);   // synchronous
 int d2d(Ctx* c, void* dst, const void* src, size_t bytes);
 int fill(Ctx* c, double* x, int64_t n, double v);
 int sync(Ctx* c);
+// Make the context's device current on the calling host thread.
+int bind(Ctx* c);
 
 // timing on the context stream
 int event_record(Ctx* c, int slot);                   // slot < 64

@@ -186,6 +186,10 @@ int d2d(Ctx* c, void* dst, const void* src, size_t bytes) {
     return 0;
 }
 int sync(Ctx* c) { return stream_sync(c); }
+int bind(Ctx* c) {
+    HIPCHK(c, hipSetDevice(c->device));
+    return 0;
+}
 int event_record(Ctx* c, int slot) {
     HIPCHK(c, hipEventRecord(c->ev[slot], c->stream));
     return 0;

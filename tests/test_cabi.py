@@ -68,3 +68,15 @@ def test_null_context_arguments(lib):
     assert lib.dmrg_sweep(None, None, 8, None) == -1
     assert lib.dmrg_energy(None, None) == -1
     lib.dmrg_destroy(None)
+
+
+def test_sweep_many_rejects_null_and_repeated_contexts(lib):
+    """Argument checks happen before any context is touched (the pointers
+    below are never dereferenced)."""
+    fake = ctypes.c_void_p(0x1000)
+    D = (ctypes.c_int32 * 2)(8, 8)
+    two = (ctypes.c_void_p * 2)(fake.value, fake.value)
+    assert lib.dmrg_sweep_many(two, 2, None, D, None) == -1
+    with_null = (ctypes.c_void_p * 2)(fake.value, None)
+    assert lib.dmrg_sweep_many(with_null, 2, None, D, None) == -1
+    assert lib.dmrg_sweep_many(None, 2, None, D, None) == -1

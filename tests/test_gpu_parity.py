@@ -178,13 +178,21 @@ def test_pairing_closed_form_pf_8p8n(pk):
 
 
 def test_sweep_many_matches_single_contexts(pk):
+    """Concurrent sweeps of independent contexts (several host threads, one
+    stream each) give the results of one-at-a-time sweeps."""
+    from workloads import batched_instances
     hs = [WORKLOADS["p_2p2n"].hamiltonian(), make_hamiltonian(make_space("sd"), 5, 2, 2, 0)]
+    hs += [w.hamiltonian() for w in batched_instances(6)]
+    precs = [0, 1] * (len(hs) // 2)
     single = []
-    for h in hs:
-        c = _ctx(pk, h, davidson_tol=1e-9, seed=3)
-        single.append(c.sweep(16)["energy"])
-    ctxs = [_ctx(pk, h, davidson_tol=1e-9, seed=3) for h in hs]
-    st, out = pk.sweep_many(ctxs, [16, 16])
+    for h, p in zip(hs, precs):
+        c = _ctx(pk, h, davidson_tol=1e-9, seed=3, precision=p)
+        single.append(c.sweep(24)["energy"])
+        c.close()
+    ctxs = [_ctx(pk, h, davidson_tol=1e-9, seed=3, precision=p) for h, p in zip(hs, precs)]
+    st, out = pk.sweep_many(ctxs, [24] * len(hs))
     assert st == 0
     for o, e in zip(out, single):
-        assert o["status"] == 0 and abs(o["energy"] - e) < 1e-10 * abs(e)
+        assert o["status"] == 0 and abs(o["energy"] - e) <= 1e-12 * abs(e)
+    for c in ctxs:
+        c.close()
