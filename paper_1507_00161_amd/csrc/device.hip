@@ -247,8 +247,13 @@ template <class T> struct MmaTraits;
 // A operand: lane l holds A[l%16][l/16]; B operand: lane l holds B[l/16][l%16].
 // Result register r of lane l is D[row(l, r)][l%16]; the row map differs
 // between the FP64 and FP32 instructions (measured on gfx950).
+// KS: K depth of one MFMA; a lane's operand fragment is 1 element (FP64, FP32)
+// or 8 consecutive k (BF16: lane l holds k = 8 (l/16) .. +7).
 template <> struct MmaTraits<double> {
     typedef d4_t acc_t;
+    typedef double frag_t;
+    typedef double scale_t;
+    static constexpr int KS = 4;
     static __device__ __forceinline__ acc_t mma(double a, double b, acc_t c) {
         return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
     }
@@ -256,11 +261,29 @@ template <> struct MmaTraits<double> {
 };
 template <> struct MmaTraits<float> {
     typedef f4_t acc_t;
+    typedef float frag_t;
+    typedef float scale_t;
+    static constexpr int KS = 4;
     static __device__ __forceinline__ acc_t mma(float a, float b, acc_t c) {
         return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
     }
     static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane >> 4) + r; }
 };
+template <> struct MmaTraits<bf16_t> {
+    typedef f4_t acc_t;
+    typedef bf8_t frag_t;
+    typedef float scale_t;
+    static constexpr int KS = 32;
+    static __device__ __forceinline__ acc_t mma(bf8_t a, bf8_t b, acc_t c) {
+        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane >> 4) + r; }
+};
+// conversions of the output type (BF16 outputs round to nearest even)
+template <class TC> __device__ __forceinline__ TC to_out(double v) { return (TC)v; }
+template <> __device__ __forceinline__ bf16_t to_out<bf16_t>(double v) { return f2bf((float)v); }
+template <class TC> __device__ __forceinline__ double from_out(TC v) { return (double)v; }
+template <> __device__ __forceinline__ double from_out<bf16_t>(bf16_t v) { return (double)bf2f(v); }
 
 // Register staging of one K slice for a 64-row operand tile (E = BK/4
 // elements per thread).  LDS holds the tile as S[r][k] (k contiguous) with
@@ -286,15 +309,26 @@ template <> __device__ __forceinline__ float bload<float>(__amdgpu_buffer_rsrc_t
 template <> __device__ __forceinline__ double bload<double>(__amdgpu_buffer_rsrc_t r, int off) {
     return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
 }
+template <> __device__ __forceinline__ bf16_t bload<bf16_t>(__amdgpu_buffer_rsrc_t r, int off) {
+    return __builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0);
+}
+// scaled value for the LDS store (BF16: scaled in FP32, rounded back)
+template <class T, class S> __device__ __forceinline__ T scaled(T v, S s) { return v * s; }
+template <> __device__ __forceinline__ bf16_t scaled<bf16_t, float>(bf16_t v, float s) {
+    return s == 1.0f ? v : f2bf(bf2f(v) * s);
+}
 
 template <class T, int BK>
 struct Slice {
     static constexpr int E = BK / 4;
-    static constexpr int LDK = BK + (sizeof(T) == 8 ? 2 : 4);
+    // row padding: 2 doubles, 4 floats, 8 bf16 (BF16 rows stay 16-byte aligned
+    // for the 8-wide fragment reads)
+    static constexpr int LDK = BK + (sizeof(T) == 8 ? 2 : (sizeof(T) == 4 ? 4 : 8));
+    typedef typename MmaTraits<T>::scale_t S;
     T v[E];
-    T scale;
+    S scale;
     // element (r, k) at P[r*ld + k]: lane -> k = t % BK, rows t / BK + (256 / BK) u
-    __device__ __forceinline__ void load_k(const T* P, int ld, int r0, int rmax, int k0, int K, T s, int tid) {
+    __device__ __forceinline__ void load_k(const T* P, int ld, int r0, int rmax, int k0, int K, S s, int tid) {
         constexpr int RS = NTH / BK;
         const int k = tid % BK, r = tid / BK;
         const bool kin = k0 + k < K;
@@ -311,7 +345,7 @@ struct Slice {
     // element (r, k) at P[k*ld + r]: lane -> r = t % 16 + 16 (t / 64), k = (t / 16) % 4 + 4 u
     // (16 consecutive r per row for coalescing; a wave's LDS stores then fall
     // in 64 different banks)
-    __device__ __forceinline__ void load_m(const T* P, int ld, int r0, int rmax, int k0, int K, T s, int tid) {
+    __device__ __forceinline__ void load_m(const T* P, int ld, int r0, int rmax, int k0, int K, S s, int tid) {
         const int r = (tid & 15) + 16 * (tid >> 6), k = (tid >> 4) & 3;
         const bool rin = r < rmax;
         const __amdgpu_buffer_rsrc_t rs = make_rsrc(P);
@@ -324,27 +358,18 @@ struct Slice {
             v[u] = bload<T>(rs, in ? base + u * step : kOutside);
         }
     }
-    __device__ __forceinline__ void store_k(T* __restrict__ S, int tid) const {
+    __device__ __forceinline__ void store_k(T* __restrict__ Sm, int tid) const {
         constexpr int RS = NTH / BK;
         const int k = tid % BK, r = tid / BK;
 #pragma unroll
-        for (int u = 0; u < E; ++u) S[(r + RS * u) * LDK + k] = v[u] * scale;
+        for (int u = 0; u < E; ++u) Sm[(r + RS * u) * LDK + k] = scaled(v[u], scale);
     }
-    __device__ __forceinline__ void store_m(T* __restrict__ S, int tid) const {
+    __device__ __forceinline__ void store_m(T* __restrict__ Sm, int tid) const {
         const int r = (tid & 15) + 16 * (tid >> 6), k = (tid >> 4) & 3;
 #pragma unroll
-        for (int u = 0; u < E; ++u) S[r * LDK + k + 4 * u] = v[u] * scale;
+        for (int u = 0; u < E; ++u) Sm[r * LDK + k + 4 * u] = scaled(v[u], scale);
     }
 };
-
-// Work-groups are dispatched round-robin over the 8 XCDs: work-group b runs
-// on XCD b % 8.  A launch gives each XCD its own task range (the host deals
-// output blocks to XCDs so that the tiles of one block share an L2).
-__device__ __forceinline__ int xcd_task(int ntasks) {
-    const int per = (ntasks + 7) >> 3;
-    const int b = blockIdx.x;
-    return (b & 7) * per + (b >> 3);
-}
 
 // Persistent grouped GEMM.  Work-group w runs its task list
 // [wg_off[w], wg_off[w+1]) (balanced on the host).  One software pipeline runs
@@ -375,11 +400,12 @@ __device__ __forceinline__ void gemm_body(const Bufs& bufs, const GemmTask* __re
     auto load = [&](const GemmTask& t, const GemmChunk& ch, int k0) {
         const T* A = (const T*)bufs.p[ch.a_buf] + ch.a_off;
         const T* B = (const T*)bufs.p[ch.b_buf] + ch.b_off;
-        const T alpha = (T)ch.alpha;
+        typedef typename MmaTraits<T>::scale_t S;
+        const S alpha = (S)ch.alpha;
         if (!ch.a_trans) ra.load_k(A, ch.lda, t.m0, t.mt, k0, ch.K, alpha, tid);
         else ra.load_m(A, ch.lda, t.m0, t.mt, k0, ch.K, alpha, tid);
-        if (!ch.b_trans) rb.load_m(B, ch.ldb, t.n0, t.nt, k0, ch.K, T(1), tid);
-        else rb.load_k(B, ch.ldb, t.n0, t.nt, k0, ch.K, T(1), tid);
+        if (!ch.b_trans) rb.load_m(B, ch.ldb, t.n0, t.nt, k0, ch.K, S(1), tid);
+        else rb.load_k(B, ch.ldb, t.n0, t.nt, k0, ch.K, S(1), tid);
     };
     auto store = [&](const GemmChunk& ch, int buf) {
         if (!ch.a_trans) ra.store_k(As[buf], tid);
@@ -415,8 +441,8 @@ __device__ __forceinline__ void gemm_body(const Bufs& bufs, const GemmTask* __re
                     const int col = wn + b * 16 + (lane & 15);
                     if (row < t.mt && col < t.nt) {
                         double v = (double)acc[a][b][r];
-                        if (t.beta) v += (double)old[a][b][r];
-                        C[base + (int64_t)row * ldc + col] = (TC)v;
+                        if (t.beta) v += from_out<TC>(old[a][b][r]);
+                        C[base + (int64_t)row * ldc + col] = to_out<TC>(v);
                     }
                     acc[a][b][r] = 0;
                 }
@@ -460,34 +486,53 @@ __device__ __forceinline__ void gemm_body(const Bufs& bufs, const GemmTask* __re
             if (more) load(ntk, nch, nk0);   // global loads in flight during the MFMAs
             const T* Ab = As[buf];
             const T* Bb = Bs[buf];
-            T av[BK / 4][2], bv[BK / 4][2];
+            typedef typename MmaTraits<T>::frag_t F;
+            constexpr int KS = MmaTraits<T>::KS, NS = BK / KS;
+            // a lane's fragment: row fr of the 16-row block, k = s KS + fk (one
+            // element) or s KS + 8 fk .. +7 (BF16, one 16-byte read)
+            auto frag = [&](const T* S, int row, int s) -> F {
+                if constexpr (sizeof(T) == 2) return *(const F*)&S[row * LDK + s * KS + 8 * fk];
+                else return S[row * LDK + s * KS + fk];
+            };
+            // FP64 / FP32: all fragments of the slice first, then the MFMAs back to
+            // back; BF16 (8 VGPRs of fragments per step): one step at a time
+            constexpr int NF = sizeof(T) == 2 ? 1 : NS;
+            F av[NF][2], bv[NF][2];
+            auto fetch = [&](int q) {
 #pragma unroll
-            for (int s4 = 0; s4 < BK / 4; ++s4) {
+                for (int a = 0; a < 2; ++a) av[q % NF][a] = frag(Ab, wm + a * 16 + fr, q);
 #pragma unroll
-                for (int a = 0; a < 2; ++a) av[s4][a] = Ab[(wm + a * 16 + fr) * LDK + 4 * s4 + fk];
+                for (int b = 0; b < 2; ++b) bv[q % NF][b] = frag(Bb, wn + b * 16 + fr, q);
+            };
+            if (NF == NS) {
 #pragma unroll
-                for (int b = 0; b < 2; ++b) bv[s4][b] = Bb[(wn + b * 16 + fr) * LDK + 4 * s4 + fk];
+                for (int q = 0; q < NS; ++q) fetch(q);
             }
             // MFMAs of 16 x 16 blocks that lie wholly outside the tile, and
-            // 4-deep K steps past the chunk's end, are skipped (wave-uniform
-            // tests): ragged sector blocks cost what they contain.
+            // K steps past the chunk's end, are skipped (wave-uniform tests):
+            // ragged sector blocks cost what they contain.
             const int kv = ch.K - k0;
             const bool am1 = wm + 16 < tk.mt, bm1 = wn + 16 < tk.nt;
             if (kv >= BK && am1 && bm1) {
 #pragma unroll
-                for (int s4 = 0; s4 < BK / 4; ++s4)
+                for (int q = 0; q < NS; ++q) {
+                    if (NF != NS) fetch(q);
 #pragma unroll
                     for (int a = 0; a < 2; ++a)
 #pragma unroll
-                        for (int b = 0; b < 2; ++b) acc[a][b] = MmaTraits<T>::mma(av[s4][a], bv[s4][b], acc[a][b]);
+                        for (int b = 0; b < 2; ++b)
+                            acc[a][b] = MmaTraits<T>::mma(av[q % NF][a], bv[q % NF][b], acc[a][b]);
+                }
             } else if (wm < tk.mt && wn < tk.nt) {
 #pragma unroll
-                for (int s4 = 0; s4 < BK / 4; ++s4) {
-                    if (4 * s4 < kv) {
-                        acc[0][0] = MmaTraits<T>::mma(av[s4][0], bv[s4][0], acc[0][0]);
-                        if (bm1) acc[0][1] = MmaTraits<T>::mma(av[s4][0], bv[s4][1], acc[0][1]);
-                        if (am1) acc[1][0] = MmaTraits<T>::mma(av[s4][1], bv[s4][0], acc[1][0]);
-                        if (am1 && bm1) acc[1][1] = MmaTraits<T>::mma(av[s4][1], bv[s4][1], acc[1][1]);
+                for (int q = 0; q < NS; ++q) {
+                    if (KS * q < kv) {
+                        if (NF != NS) fetch(q);
+                        const int f = q % NF;
+                        acc[0][0] = MmaTraits<T>::mma(av[f][0], bv[f][0], acc[0][0]);
+                        if (bm1) acc[0][1] = MmaTraits<T>::mma(av[f][0], bv[f][1], acc[0][1]);
+                        if (am1) acc[1][0] = MmaTraits<T>::mma(av[f][1], bv[f][0], acc[1][0]);
+                        if (am1 && bm1) acc[1][1] = MmaTraits<T>::mma(av[f][1], bv[f][1], acc[1][1]);
                     }
                 }
             }
@@ -541,133 +586,13 @@ __global__ void __launch_bounds__(NTH, 4) k_heff_y(Bufs b, const GemmTask* t, co
     gemm_body<T, TC, BK>(b, t, c, s);
 }
 
-// ---- BF16: K slice 32, one v_mfma_f32_16x16x32_bf16 per 16x16 block and slice
-// LDS holds fp32-converted-to-bf16 values as As[m][k] and Bs[n][k] (k fastest)
-// so that a lane's 8 consecutive k values are one 16-byte read.
-__device__ __forceinline__ void stage_a_bf(bf16_t* __restrict__ As, const bf16_t* __restrict__ A,
-                                           const GemmChunk& ch, int m0, int mt, int k0, float alpha, int tid) {
-    constexpr int BK = 32, LDS = BK + 8;
-    // 64 rows x 32 k = 2048 elements, 8 per thread
-    if (!ch.a_trans) {
-        int m = tid >> 2, kk = (tid & 3) * 8;
-        const bf16_t* src = A + (int64_t)(m0 + m) * ch.lda + k0 + kk;
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            int k = k0 + kk + u;
-            float v = (m < mt && k < ch.K) ? bf2f(src[u]) : 0.f;
-            As[m * LDS + kk + u] = f2bf(v * alpha);
-        }
-    } else {
-        int kk = tid >> 3, m = (tid & 7) * 8;
-        int k = k0 + kk;
-        const bf16_t* src = A + (int64_t)k * ch.lda + m0 + m;
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            float v = (m + u < mt && k < ch.K) ? bf2f(src[u]) : 0.f;
-            As[(m + u) * LDS + kk] = f2bf(v * alpha);
-        }
-    }
-}
-__device__ __forceinline__ void stage_b_bf(bf16_t* __restrict__ Bs, const bf16_t* __restrict__ B,
-                                           const GemmChunk& ch, int n0, int nt, int k0, int tid) {
-    constexpr int BK = 32, LDS = BK + 8;
-    if (!ch.b_trans) {
-        int kk = tid >> 3, n = (tid & 7) * 8;
-        int k = k0 + kk;
-        const bf16_t* src = B + (int64_t)k * ch.ldb + n0 + n;
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            bf16_t v = (n + u < nt && k < ch.K) ? src[u] : (bf16_t)0;
-            Bs[(n + u) * LDS + kk] = v;
-        }
-    } else {
-        int n = tid >> 2, kk = (tid & 3) * 8;
-        const bf16_t* src = B + (int64_t)(n0 + n) * ch.ldb + k0 + kk;
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            int k = k0 + kk + u;
-            bf16_t v = (n < nt && k < ch.K) ? src[u] : (bf16_t)0;
-            Bs[n * LDS + kk + u] = v;
-        }
-    }
-}
-
-template <class TC>
-__global__ void __launch_bounds__(NTH) k_gemm_bf16(Bufs bufs, const GemmTask* __restrict__ tasks,
-                                                   const GemmChunk* __restrict__ chunks, int ntasks) {
-    constexpr int BK = 32, LDS = BK + 8;
-    __shared__ __attribute__((aligned(16))) bf16_t As[TM * LDS];
-    __shared__ __attribute__((aligned(16))) bf16_t Bs[TN * LDS];
-    const int ti = xcd_task(ntasks);
-    if (ti >= ntasks) return;
-    const GemmTask tk = tasks[ti];
-    if (tk.chunk_begin == tk.chunk_end && tk.beta) return;
-    const int tid = threadIdx.x;
-    const int wave = tid >> 6, lane = tid & 63;
-    const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
-    f4_t acc[2][2];
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int b = 0; b < 2; ++b) acc[a][b] = f4_t{0, 0, 0, 0};
-    for (int c = tk.chunk_begin; c < tk.chunk_end; ++c) {
-        const GemmChunk ch = chunks[c];
-        const bf16_t* A = (const bf16_t*)bufs.p[ch.a_buf] + ch.a_off;
-        const bf16_t* B = (const bf16_t*)bufs.p[ch.b_buf] + ch.b_off;
-        const float alpha = (float)ch.alpha;
-        for (int k0 = 0; k0 < ch.K; k0 += BK) {
-            stage_a_bf(As, A, ch, tk.m0, tk.mt, k0, alpha, tid);
-            stage_b_bf(Bs, B, ch, tk.n0, tk.nt, k0, tid);
-            __syncthreads();
-            // lane: row/col lane%16, k 8*(lane/16)..+7
-            const int kq = 8 * (lane >> 4);
-            bf8_t av[2], bv[2];
-#pragma unroll
-            for (int a = 0; a < 2; ++a)
-                av[a] = *(const bf8_t*)&As[(wm + a * 16 + (lane & 15)) * LDS + kq];
-#pragma unroll
-            for (int b = 0; b < 2; ++b)
-                bv[b] = *(const bf8_t*)&Bs[(wn + b * 16 + (lane & 15)) * LDS + kq];
-#pragma unroll
-            for (int a = 0; a < 2; ++a)
-#pragma unroll
-                for (int b = 0; b < 2; ++b)
-                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[a], bv[b], acc[a][b], 0, 0, 0);
-            __syncthreads();
-        }
-    }
-    TC* C = (TC*)bufs.p[tk.c_buf] + tk.c_off;
-    const int64_t ldc = tk.c_local ? TN : tk.ldc;
-    const int64_t base = tk.c_local ? 0 : (int64_t)tk.m0 * tk.ldc + tk.n0;
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int b = 0; b < 2; ++b)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                int row = wm + a * 16 + 4 * (lane >> 4) + r;
-                int col = wn + b * 16 + (lane & 15);
-                if (row < tk.mt && col < tk.nt) {
-                    TC* dst = C + base + (int64_t)row * ldc + col;
-                    float v = acc[a][b][r];
-                    if constexpr (sizeof(TC) == 4) {
-                        if (tk.beta) v += *(float*)dst;
-                        *(float*)dst = v;
-                    } else {
-                        if (tk.beta) v += bf2f(*(bf16_t*)dst);
-                        *(bf16_t*)dst = f2bf(v);
-                    }
-                }
-            }
-}
-
 int gemm(Ctx* c, int ab, int cp, void* const* bufs, const GemmTask* tasks, const Sched& sc,
          const GemmChunk* chunks, int kind) {
     const int ntasks = sc.ntasks;
     if (ntasks <= 0) return 0;
     Bufs b;
     for (int i = 0; i < kMaxBufs; ++i) b.p[i] = bufs[i];
-    dim3 pgrid(std::max(1, sc.nwg)), block(NTH), grid(((ntasks + 7) / 8) * 8);
+    dim3 pgrid(std::max(1, sc.nwg)), block(NTH);
     if (ab == P_F64 && cp == P_F64) {
         if (kind == GK_HEFF_Z)
             hipLaunchKernelGGL((k_heff_z<double, double, 16>), pgrid, block, 0, c->stream, b, tasks, chunks, sc);
@@ -683,10 +608,21 @@ int gemm(Ctx* c, int ab, int cp, void* const* bufs, const GemmTask* tasks, const
         else
             hipLaunchKernelGGL((k_gemm<float, float, 32>), pgrid, block, 0, c->stream, b, tasks, chunks, sc);
     }
-    else if (ab == P_BF16 && cp == P_F32)
-        hipLaunchKernelGGL((k_gemm_bf16<float>), grid, block, 0, c->stream, b, tasks, chunks, ntasks);
-    else if (ab == P_BF16 && cp == P_BF16)
-        hipLaunchKernelGGL((k_gemm_bf16<bf16_t>), grid, block, 0, c->stream, b, tasks, chunks, ntasks);
+    else if (ab == P_BF16 && cp == P_F32) {
+        if (kind == GK_HEFF_Z)
+            hipLaunchKernelGGL((k_heff_z<bf16_t, float, 32>), pgrid, block, 0, c->stream, b, tasks, chunks, sc);
+        else if (kind == GK_HEFF_Y)
+            hipLaunchKernelGGL((k_heff_y<bf16_t, float, 32>), pgrid, block, 0, c->stream, b, tasks, chunks, sc);
+        else
+            hipLaunchKernelGGL((k_gemm<bf16_t, float, 32>), pgrid, block, 0, c->stream, b, tasks, chunks, sc);
+    } else if (ab == P_BF16 && cp == P_BF16) {
+        if (kind == GK_HEFF_Z)
+            hipLaunchKernelGGL((k_heff_z<bf16_t, bf16_t, 32>), pgrid, block, 0, c->stream, b, tasks, chunks, sc);
+        else if (kind == GK_HEFF_Y)
+            hipLaunchKernelGGL((k_heff_y<bf16_t, bf16_t, 32>), pgrid, block, 0, c->stream, b, tasks, chunks, sc);
+        else
+            hipLaunchKernelGGL((k_gemm<bf16_t, bf16_t, 32>), pgrid, block, 0, c->stream, b, tasks, chunks, sc);
+    }
     else {
         c->err = "unsupported GEMM precision combination";
         return 1;

@@ -30,6 +30,9 @@ CASES = [
     ("sd_4p4n_D32", "sd_4p4n", None, [32, 32, 32]),
     ("sd_3p2n_M1_rand_D24", ("sd", 13, 3, 2, 1), 5, [24, 24]),
     ("pf_8p8n_D32", "pf_8p8n", None, [32, 32]),
+    # pf + g9/2 (60 sites, 12p + 12n, the 64Ge-sized space), J_z = 0 and J_z = 2
+    ("pfg9_12p12n_D16", "pfg9_12p12n", None, [16, 16]),
+    ("pfg9_12p12n_M2_D16", "pfg9_12p12n_M2", None, [16]),
 ]
 
 

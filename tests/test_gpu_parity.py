@@ -135,7 +135,7 @@ def _golden_ham(spec):
 
 
 @pytest.mark.parametrize("name", ["p_2p2n_D64", "p_2p2n_M2_D16", "sd_4p4n_D32", "sd_3p2n_M1_rand_D24",
-                                  "pf_8p8n_D32"])
+                                  "pf_8p8n_D32", "pfg9_12p12n_D16", "pfg9_12p12n_M2_D16"])
 @pytest.mark.parametrize("precision,rtol", [(0, 1e-8), (1, 1e-6), (2, 1e-6)])
 def test_sweep_energies_match_oracle(pk, name, precision, rtol):
     g = _golden()
@@ -151,6 +151,24 @@ def test_sweep_energies_match_oracle(pk, name, precision, rtol):
         if "exact" in case:
             assert r["energy"] >= case["exact"] - 1e-9        # variational bound
     assert c.energy() == r["energy"]
+
+
+@pytest.mark.parametrize("name", ["pfg9_12p12n", "pfg9_12p12n_M2"])
+def test_pfg9_ramp_lowers_the_energy(pk, name):
+    """The 60-site pf + g9/2 space (12p + 12n, J_z = 0 and 2) on a short ramp
+    in mixed FP32: each sweep stays at or below the previous one and below
+    the oracle's D = 16 energies."""
+    g = _golden()["cases"][name + "_D16"]
+    h = WORKLOADS[name].hamiltonian()
+    c = _ctx(pk, h, precision=1, davidson_tol=1e-7, noise=1e-4, noise_sweeps=1, seed=7)
+    prev = None
+    for D in (32, 64, 128):
+        r = c.sweep(D)
+        assert r["code"] in (0, 1) and np.isfinite(r["energy"])
+        if prev is not None:
+            assert r["energy"] <= prev + 1e-7
+        prev = r["energy"]
+    assert prev < min(g["energies"])
 
 
 def test_p_shell_exact_bond_dimension_equals_ed(pk):
