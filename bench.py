@@ -49,7 +49,8 @@ def run_schedule(workload, prec: str, warmup: int, steps: int, D_main: int, seed
         D = ramp[w] if w < len(ramp) else D_main
         t = time.perf_counter()
         r = ctx.sweep(D)
-        log(f"[{prec}] warmup sweep {w} D={D}: E={r['energy']:.9f} {time.perf_counter() - t:.1f}s")
+        log(f"[{prec}] warmup sweep {w} D={D}: E={r['energy']:.9f} {time.perf_counter() - t:.1f}s "
+            f"products lo/64={r['products_low']}/{r['products_fp64']} not converged {r['not_converged']}")
     torch.cuda.synchronize()
     tot = {}
     walls = []
@@ -65,7 +66,7 @@ def run_schedule(workload, prec: str, warmup: int, steps: int, D_main: int, seed
             if isinstance(v, (int, float)) and key not in ("energy", "last_theta", "code", "status"):
                 tot[key] = tot.get(key, 0) + v
         log(f"[{prec}] timed sweep {k} D={D_main}: E={r['energy']:.9f} {walls[-1]:.2f}s "
-            f"products lo/64={r['products_low']}/{r['products_fp64']} "
+            f"products lo/64={r['products_low']}/{r['products_fp64']} not converged {r['not_converged']} "
             f"heff {r['heff_flops'] / max(r['heff_seconds'], 1e-12) / 1e12:.2f} TF/s; "
             f"time in products {r['heff_seconds']:.2f}s, truncation+renorm+prediction "
             f"{r['renorm_seconds']:.2f}s (density {r['density_seconds']:.2f}, eig {r['eig_seconds']:.2f}, "

@@ -1411,79 +1411,122 @@ dmrg_status Engine::setup_bond(int b, std::unique_ptr<Bond>& outp) {
     return DMRG_OK;
 }
 
-// Two launches per product: Z = psi_sub op(B)^T for every term with an E
-// operator, then every output sub-block accumulates op(A) Z (or psi op(B)^T,
-// or op(A) psi) over all its terms in one tile task (no atomics).  Terms are
-// grouped so that each group's Z fits the scratch budget; the first group
-// writes every output sub-block, later groups accumulate.
+// Launches per product: phase 1 forms Z_t[x, i] = psi_x[i, :] op(B_t)^T for
+// every term t with an E operator, one row block per input S sub-sector i,
+// spanning the full width of the output E sector (its sub-sectors side by
+// side; columns a term does not reach are cleared).  Phase 2 then gives
+// every output row block Y[x2, i2, :] (full E width) all of its terms as one
+// stacked-K chunk list: sum_t alpha op(A_t)[i2 <- i] Z_t[x, i] (or op(A) psi
+// for the S-only term).  The E-only term (1 x H_E) is a third, small launch
+// that accumulates psi op(B)^T into the sub-blocks.  Terms are grouped so
+// that each group's Z fits the scratch budget; the first group writes every
+// output block, later groups accumulate.
 // bufs: 0 S ops, 1 E ops, 2 x, 3 Z, 4 y.
 dmrg_status Engine::build_heff_plan(Bond& B) {
     const Enl &S = B.S, &E = B.E;
     const int nb = (int)B.pm_S.size();
+    auto yid = [&](int x, int i2) { return x * 2 + S.sub[i2].sigma; };
     auto subid = [&](int x, int i, int j) { return x * 4 + S.sub[i].sigma * 2 + E.sub[j].sigma; };
     const int64_t zbudget =
         opt_.scratch_bytes ? (int64_t)(opt_.scratch_bytes / sizeof(double)) : ((int64_t)1 << 31);
-    struct Out {
-        int x, i, j;
-    };
-    std::vector<Out> outs(nb * 4, Out{-1, -1, -1});
+    std::vector<std::pair<int, int>> rows(nb * 2, {-1, -1});   // yid -> (x, i2)
     for (int x = 0; x < nb; ++x)
         for (int i : S.msub[B.pm_S[x]])
-            for (int j : E.msub[B.pm_E[x]])
-                if (i >= 0 && j >= 0) outs[subid(x, i, j)] = {x, i, j};
+            if (i >= 0) rows[yid(x, i)] = {x, i};
 
-    // work of one term, Z offsets relative to the term's own Z
-    struct ZBlk {
-        int64_t xoff, boff, zoff;
-        int ldx, ldb, K, M, Nn;
-        bool btr;
+    // one Z output block (a sub-sector's columns of a term's Z row block)
+    struct ZOut {
+        int64_t zoff;   // relative to the term's own Z
+        int ldz, M, N;
+        std::vector<GemmChunk> chunks;
     };
     struct TermWork {
-        std::vector<ZBlk> z;
-        std::vector<std::pair<int, GemmChunk>> c2;
+        std::vector<ZOut> z;
+        std::vector<std::pair<int, GemmChunk>> c2;   // (yid, chunk); Z offsets relative
+        std::vector<std::pair<int, GemmChunk>> c3;   // (subid, chunk) of the E-only term
         int64_t zsize = 0;
     };
+    auto leaves = [&]() { return fail(DMRG_ERR_DEVICE, "internal: H_eff term leaves the target sector"); };
     auto work = [&](const Term& tm, TermWork& w) -> dmrg_status {
         const Op* A = tm.a >= 0 ? &B.Sops.ops[tm.a] : nullptr;
         const Op* Bo = tm.b >= 0 ? &B.Eops.ops[tm.b] : nullptr;
-        static const std::vector<int> one_none = {-1};
+        auto alpha_of = [&](int i, int i2) {
+            double sg = 1.0;
+            if (tm.par) sg = ((tm.sign_out ? S.sub[i2].q.n() : S.sub[i].q.n()) & 1) ? -1.0 : 1.0;
+            return tm.coef * sg;
+        };
         for (int x = 0; x < nb; ++x) {
             const int mS = B.pm_S[x], mE = B.pm_E[x];
             const int ldx = E.md[mE];
             for (int i : S.msub[mS]) {
                 if (i < 0) continue;
-                for (int ai : A ? A->acting(i, tm.ta) : one_none) {
-                    const Blk* ab = ai >= 0 ? &A->blk[ai] : nullptr;
-                    const int i2 = ab ? (tm.ta ? ab->in : ab->out) : i;
-                    for (int j : E.msub[mE]) {
-                        if (j < 0) continue;
-                        for (int bi : Bo ? Bo->acting(j, tm.tb) : one_none) {
-                            const Blk* bb = bi >= 0 ? &Bo->blk[bi] : nullptr;
-                            const int j2 = bb ? (tm.tb ? bb->in : bb->out) : j;
-                            const int x2 = B.blk_of_S[S.sub[i2].m];
-                            if (x2 < 0 || B.pm_E[x2] != E.sub[j2].m)
-                                return fail(DMRG_ERR_DEVICE, "internal: H_eff term leaves the target sector");
-                            double sg = 1.0;
-                            if (tm.par) sg = ((tm.sign_out ? S.sub[i2].q.n() : S.sub[i].q.n()) & 1) ? -1.0 : 1.0;
-                            const double alpha = tm.coef * sg;
-                            const int64_t xoff = B.poff[x] + (int64_t)S.sub[i].off * ldx + E.sub[j].off;
-                            const int di = S.sub[i].dim, dj = E.sub[j].dim, dj2 = E.sub[j2].dim;
-                            GemmChunk c{};
-                            if (ab && bb) {
-                                const int64_t zo = w.zsize;
-                                w.zsize += ((int64_t)di * dj2 + 7) / 8 * 8;
-                                w.z.push_back({xoff, bb->off, zo, ldx, bb->cols, dj, di, dj2, !tm.tb});
-                                c = GemmChunk{alpha, ab->off, zo, ab->cols, dj2, di, 0, 3, (uint8_t)tm.ta, 0};
-                            } else if (ab) {
-                                c = GemmChunk{alpha, ab->off, xoff, ab->cols, ldx, di, 0, 2, (uint8_t)tm.ta, 0};
-                            } else if (bb) {
-                                c = GemmChunk{alpha, xoff, bb->off, ldx, bb->cols, dj, 2, 1, 0, (uint8_t)!tm.tb};
-                            } else {
-                                continue;
-                            }
-                            w.c2.push_back({subid(x2, i2, j2), c});
-                        }
+                const int di = S.sub[i].dim;
+                const int64_t xrow = B.poff[x] + (int64_t)S.sub[i].off * ldx;
+                if (!Bo) {   // S-only term: op(A) psi over the full width
+                    if (!A) continue;
+                    for (int ai : A->acting(i, tm.ta)) {
+                        const Blk& ab = A->blk[ai];
+                        const int i2 = tm.ta ? ab.in : ab.out;
+                        const int x2 = B.blk_of_S[S.sub[i2].m];
+                        if (x2 < 0 || B.pm_E[x2] != mE) return leaves();
+                        w.c2.push_back({yid(x2, i2), GemmChunk{alpha_of(i, i2), ab.off, xrow, ab.cols, ldx, di, 0, 2,
+                                                               (uint8_t)tm.ta, 0}});
                     }
+                    continue;
+                }
+                // E operator: which input sub-sectors j feed which output sub-sector j2
+                std::vector<std::pair<int, int>> feeds[2];   // per output sigma: (j, block)
+                int mE2 = -1;
+                for (int j : E.msub[mE]) {
+                    if (j < 0) continue;
+                    for (int bi : Bo->acting(j, tm.tb)) {
+                        const Blk& bb = Bo->blk[bi];
+                        const int j2 = tm.tb ? bb.in : bb.out;
+                        if (mE2 >= 0 && E.sub[j2].m != mE2) return leaves();
+                        mE2 = E.sub[j2].m;
+                        feeds[E.sub[j2].sigma].push_back({j, bi});
+                    }
+                }
+                if (mE2 < 0) continue;
+                if (!A) {   // E-only term: psi op(B)^T into the sub-blocks (third launch)
+                    const int x2 = B.blk_of_S[S.sub[i].m];
+                    if (x2 < 0 || B.pm_E[x2] != mE2) return leaves();
+                    for (int sg = 0; sg < 2; ++sg)
+                        for (auto& f : feeds[sg]) {
+                            const Blk& bb = Bo->blk[f.second];
+                            const int j = f.first, j2 = tm.tb ? bb.in : bb.out;
+                            w.c3.push_back({subid(x2, i, j2),
+                                            GemmChunk{alpha_of(i, i), xrow + E.sub[j].off, bb.off, ldx, bb.cols,
+                                                      E.sub[j].dim, 2, 1, 0, (uint8_t)!tm.tb}});
+                        }
+                    continue;
+                }
+                // Z_t[x, i]: d_i x NE2, sub-sector j2 at its column offset
+                const int NE2 = E.md[mE2];
+                const int64_t zo = w.zsize;
+                w.zsize += ((int64_t)di * NE2 + 7) / 8 * 8;
+                for (int j2 : E.msub[mE2]) {
+                    if (j2 < 0) continue;
+                    ZOut out;
+                    out.zoff = zo + E.sub[j2].off;
+                    out.ldz = NE2;
+                    out.M = di;
+                    out.N = E.sub[j2].dim;
+                    for (auto& f : feeds[E.sub[j2].sigma]) {
+                        const Blk& bb = Bo->blk[f.second];
+                        const int j = f.first;
+                        out.chunks.push_back(GemmChunk{1.0, xrow + E.sub[j].off, bb.off, ldx, bb.cols, E.sub[j].dim, 2,
+                                                       1, 0, (uint8_t)!tm.tb});
+                    }
+                    w.z.push_back(std::move(out));   // no chunks: the columns are cleared
+                }
+                for (int ai : A->acting(i, tm.ta)) {
+                    const Blk& ab = A->blk[ai];
+                    const int i2 = tm.ta ? ab.in : ab.out;
+                    const int x2 = B.blk_of_S[S.sub[i2].m];
+                    if (x2 < 0 || B.pm_E[x2] != mE2) return leaves();
+                    w.c2.push_back(
+                        {yid(x2, i2), GemmChunk{alpha_of(i, i2), ab.off, zo, ab.cols, NE2, di, 0, 3, (uint8_t)tm.ta, 0}});
                 }
             }
         }
@@ -1492,28 +1535,44 @@ dmrg_status Engine::build_heff_plan(Bond& B) {
 
     B.groups.clear();
     B.flops = 0.0;
-    std::vector<std::vector<GemmChunk>> lists(nb * 4);
+    std::vector<std::vector<GemmChunk>> lists(nb * 2), lists3(nb * 4);
     GB g1;
     int64_t z = 0;
     bool first = true;
     auto close_group = [&]() -> dmrg_status {
         HeffGroup grp;
         grp.z_elems = z;
-        GB g2;
-        for (int id = 0; id < nb * 4; ++id) {
-            const Out& o = outs[id];
-            if (o.x < 0) continue;
+        GB g2, g3;
+        for (int id = 0; id < nb * 2; ++id) {
+            const int x = rows[id].first, i2 = rows[id].second;
+            if (x < 0) continue;
             auto& l = lists[id];
             if (!first && l.empty()) continue;
             g2.begin();
             g2.chunks.insert(g2.chunks.end(), l.begin(), l.end());
-            const int ldy = E.md[B.pm_E[o.x]];
-            const int64_t yoff = B.poff[o.x] + (int64_t)S.sub[o.i].off * ldy + E.sub[o.j].off;
-            g2.end(4, yoff, ldy, S.sub[o.i].dim, E.sub[o.j].dim, first ? 0 : 1);
+            const int ldy = E.md[B.pm_E[x]];
+            g2.end(4, B.poff[x] + (int64_t)S.sub[i2].off * ldy, ldy, S.sub[i2].dim, ldy, first ? 0 : 1);
+            l.clear();
+        }
+        for (int id = 0; id < nb * 4; ++id) {
+            auto& l = lists3[id];
+            if (l.empty()) continue;
+            const int x = id / 4;
+            int i = -1, j = -1;
+            for (int ii : S.msub[B.pm_S[x]])
+                if (ii >= 0 && S.sub[ii].sigma == (id & 3) / 2) i = ii;
+            for (int jj : E.msub[B.pm_E[x]])
+                if (jj >= 0 && E.sub[jj].sigma == (id & 1)) j = jj;
+            if (i < 0 || j < 0) return fail(DMRG_ERR_DEVICE, "internal: E-only term without its sub-block");
+            g3.begin();
+            g3.chunks.insert(g3.chunks.end(), l.begin(), l.end());
+            const int ldy = E.md[B.pm_E[x]];
+            g3.end(4, B.poff[x] + (int64_t)S.sub[i].off * ldy + E.sub[j].off, ldy, S.sub[i].dim, E.sub[j].dim, 1);
             l.clear();
         }
         TRY(finish_plans(*this, g1, grp.p1, g2, grp.p2));
-        B.flops += grp.p1.flops + grp.p2.flops;
+        TRY(finish_plan(*this, g3, grp.p3));
+        B.flops += grp.p1.flops + grp.p2.flops + grp.p3.flops;
         B.groups.push_back(std::move(grp));
         g1 = GB();
         z = 0;
@@ -1524,16 +1583,17 @@ dmrg_status Engine::build_heff_plan(Bond& B) {
         TermWork w;
         TRY(work(tm, w));
         if (z > 0 && z + w.zsize > zbudget) TRY(close_group());
-        for (const ZBlk& zb : w.z) {
+        for (ZOut& zb : w.z) {
             g1.begin();
-            g1.chunk(1.0, 2, zb.xoff, zb.ldx, false, 1, zb.boff, zb.ldb, zb.btr, zb.K);
-            g1.end(3, z + zb.zoff, zb.Nn, zb.M, zb.Nn, 0);
+            g1.chunks.insert(g1.chunks.end(), zb.chunks.begin(), zb.chunks.end());
+            g1.end(3, z + zb.zoff, zb.ldz, zb.M, zb.N, 0);
         }
         for (auto& pc : w.c2) {
             GemmChunk c = pc.second;
             if (c.b_buf == 3) c.b_off += z;
             lists[pc.first].push_back(c);
         }
+        for (auto& pc : w.c3) lists3[pc.first].push_back(pc.second);
         z += w.zsize;
     }
     TRY(close_group());
@@ -1638,10 +1698,9 @@ dmrg_status Engine::heff_launch(Bond& B, const double* x, double* y, int prec, b
             TRY(run_gemm(prec, bufs, B.groups[g].p1, -1, dmrgdev::GK_HEFF_Z));
             if (timed) DEV(dmrgdev::event_record(dev_, 3));
             TRY(run_gemm(prec, bufs, B.groups[g].p2, -1, dmrgdev::GK_HEFF_Y, timed ? 4 : -1));
-            if (timed) {
-                DEV(dmrgdev::event_record(dev_, 5));
-                if (opt_.precision == DMRG_FP64) account(B.groups[g], es, es);
-            }
+            if (timed) DEV(dmrgdev::event_record(dev_, 5));
+            TRY(run_gemm(prec, bufs, B.groups[g].p3));
+            if (timed && opt_.precision == DMRG_FP64) account(B.groups[g], es, es);
         }
         return DMRG_OK;
     }
@@ -1660,10 +1719,9 @@ dmrg_status Engine::heff_launch(Bond& B, const double* x, double* y, int prec, b
         TRY(run_gemm(prec, bufs, B.groups[g].p1, prec, dmrgdev::GK_HEFF_Z));   // Z in the operand precision
         if (timed) DEV(dmrgdev::event_record(dev_, 3));
         TRY(run_gemm(prec, bufs, B.groups[g].p2, dmrgdev::P_F32, dmrgdev::GK_HEFF_Y, timed ? 4 : -1));
-        if (timed) {
-            DEV(dmrgdev::event_record(dev_, 5));
-            account(B.groups[g], es, es);
-        }
+        if (timed) DEV(dmrgdev::event_record(dev_, 5));
+        TRY(run_gemm(prec, bufs, B.groups[g].p3, dmrgdev::P_F32));
+        if (timed) account(B.groups[g], es, es);
     }
     DEV(dmrgdev::convert(dev_, dmrgdev::P_F32, ylo_.p, dmrgdev::P_F64, y, B.dim));
     return DMRG_OK;
@@ -1820,7 +1878,9 @@ dmrg_status Engine::davidson(Bond& B, double* theta_out, int64_t* nlo, int64_t* 
             break;
         }
         DEV(dmrgdev::copy_scaled_inv_norm(dev_, dv_t_.d(), n, sc + 2, Vm + (size_t)k * n));
-        const bool low = mixed && refreshes < max_refresh;
+        // reduced precision while refreshes last and half the product budget is
+        // left; after that the solve finishes as a plain FP64 Davidson
+        const bool low = mixed && refreshes < max_refresh && *nlo + *n64 < opt_.davidson_max_iter / 2;
         TRY(heff(B, Vm + (size_t)k * n, Wm + (size_t)k * n, low ? lowp : dmrgdev::P_F64));
         (low ? *nlo : *n64) += 1;
         if (low) exact = false;

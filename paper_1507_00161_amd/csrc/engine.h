@@ -224,7 +224,8 @@ struct GemmPlan {
 };
 
 struct HeffGroup {
-    GemmPlan p1, p2;    // Z = psi op(B)^T ; y (+)= op(A) Z
+    GemmPlan p1, p2;    // Z = psi op(B)^T ; y (+)= op(A) Z over full-width row blocks
+    GemmPlan p3;        // y += psi op(B)^T of the E-only term, into sub-blocks
     int64_t z_elems = 0;
 };
 
