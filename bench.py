@@ -110,24 +110,31 @@ def cpu_baseline(budget_s: float = 20.0):
                       f"merged-sector matmul flops / time in H_eff products"}
 
 
-KERNEL_SRC = os.path.join(ROOT, "paper_1507_00161_amd", "csrc", "device.hip")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_heff_y_f32_pf_8p8n_D2048_traffic.txt")
+# the kernels and the engine that builds their task lists: counters taken for
+# other sources do not describe the current launches
+KERNEL_SRCS = [os.path.join(ROOT, "paper_1507_00161_amd", "csrc", f) for f in ("device.hip", "engine.cpp")]
+# HBM traffic summaries of the two H_eff GEMM phases (FP32, benchmark workload)
+TRAFFIC_FILES = {"k_heff_y<float, float, 32>": os.path.join(ROOT, "profiles", "k_heff_y_f32_pf_8p8n_D2048_traffic.txt"),
+                 "k_heff_z<float, float, 32>": os.path.join(ROOT, "profiles", "k_heff_z_f32_pf_8p8n_D2048_traffic.txt")}
 
 
 def source_sha() -> str:
     import hashlib
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()
+    h = hashlib.sha256()
+    for path in KERNEL_SRCS:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
-def measured_traffic():
-    """HBM bytes per launch of the phase-2 kernel from the committed counter
-    summary, or None when the kernel source changed since it was taken."""
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from its committed counter summary, or
+    None when there is none or the kernel source changed since it was taken."""
     try:
-        kv = dict(l.strip().split("=", 1) for l in open(TRAFFIC_FILE) if "=" in l and not l.startswith("#"))
-    except OSError:
+        kv = dict(l.strip().split("=", 1) for l in open(TRAFFIC_FILES[kernel]) if "=" in l and not l.startswith("#"))
+    except (OSError, KeyError):
         return None
-    if kv.get("device_hip_sha256") != source_sha():
+    if kv.get("sources_sha256") != source_sha():
         return None
     return float(kv["hbm_bytes_per_launch"])
 
@@ -155,6 +162,7 @@ def summarize_trace(d, bench_json, kernel):
     benchmark: the kernel table, and the average duration of `kernel` over the
     timed sweeps (its last N dispatches, N from the benchmark's own line)."""
     b = json.loads([l for l in open(bench_json) if l.startswith("{")][-1])
+    kernel = kernel or b["roofline"]["kernel"]
     n = int(b["roofline"]["launches"])
     stats = _csv_rows(_find(d, "kernel_stats.csv"))
     trace = _csv_rows(_find(d, "kernel_trace.csv"))
@@ -178,7 +186,8 @@ def summarize_counters(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, ben
     runs (FETCH_SIZE, WRITE_SIZE in KiB per dispatch), each scaled by what the
     same counter reads for a plain copy of known size."""
     b = json.loads([l for l in open(bench_json) if l.startswith("{")][-1])
-    n = int(b["roofline"]["launches"])
+    n = int(b["roofline"]["launches"])   # both H_eff phases launch once per product and group
+    kernel = kernel or b["roofline"]["kernel"]
 
     def per_dispatch(d, counter, match):
         rows = [r for r in _csv_rows(_find(d, "counter_collection.csv"))
@@ -205,7 +214,7 @@ def summarize_counters(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, ben
     print(f"fetch_bytes_per_launch={fetch:.6g}")
     print(f"write_bytes_per_launch={write:.6g}")
     print(f"hbm_bytes_per_launch={fetch + write:.6g}")
-    print(f"device_hip_sha256={source_sha()}")
+    print(f"sources_sha256={source_sha()}")
 
 
 def copy_reference(mib):
@@ -272,7 +281,7 @@ def main():
     ap.add_argument("--summarize-counters", nargs=4, metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE"),
                     help="HBM traffic from rocprofv3 --pmc runs of this benchmark and of --copy-reference")
     ap.add_argument("--bench-json", help="the benchmark line of the profiled run")
-    ap.add_argument("--kernel", default="k_heff_y<float, float, 32>")
+    ap.add_argument("--kernel", help="kernel to summarise (default: the benchmark line's roofline kernel)")
     ap.add_argument("--copy-reference", type=int, metavar="MIB", help="one plain device copy of MIB MiB")
     ap.add_argument("--batched", type=int, metavar="K",
                     help="independent small solves: K instances one at a time vs dmrg_sweep_many")
@@ -315,7 +324,7 @@ def main():
     achieved = kfl / max(kdt, 1e-12) / 1e12
     ctype = {"fp64": "double, double, 16", "fp32": "float, float, 32"}.get(main_p, "")
     kname = f"{'k_heff_y' if k == 'gemm2' else 'k_heff_z'}<{ctype}>" if ctype else "k_gemm_bf16"
-    traffic = measured_traffic() if (k == "gemm2" and main_p == "fp32") else None
+    traffic = measured_traffic(kname)
     out = {
         "metric": "Davidson H_eff·psi TFLOP/s + sweep time at D=2048, mixed vs FP64, |dE|<1e-6",
         "value": value,
