@@ -1458,6 +1458,51 @@ dmrg_status Engine::build_heff_plan(Bond& B) {
         for (int x = 0; x < nb; ++x) {
             const int mS = B.pm_S[x], mE = B.pm_E[x];
             const int ldx = E.md[mE];
+            // When the S operator acts on every sub-sector of this block, Z_t for
+            // the whole block (all its rows) is formed at once: taller phase-1
+            // output blocks, one operator read per block row tile.
+            bool zrow_done = false;
+            int64_t zrow = 0;
+            int NE2x = 0;
+            if (A && Bo) {
+                bool all = true;
+                for (int i : S.msub[mS])
+                    if (i >= 0 && A->acting(i, tm.ta).empty()) all = false;
+                std::vector<std::pair<int, int>> fd[2];
+                int m2 = -1;
+                for (int j : E.msub[mE]) {
+                    if (j < 0) continue;
+                    for (int bi : Bo->acting(j, tm.tb)) {
+                        const Blk& bb = Bo->blk[bi];
+                        const int j2 = tm.tb ? bb.in : bb.out;
+                        if (m2 >= 0 && E.sub[j2].m != m2) return leaves();
+                        m2 = E.sub[j2].m;
+                        fd[E.sub[j2].sigma].push_back({j, bi});
+                    }
+                }
+                if (all && m2 >= 0) {
+                    NE2x = E.md[m2];
+                    const int dS = S.md[mS];
+                    zrow = w.zsize;
+                    w.zsize += ((int64_t)dS * NE2x + 7) / 8 * 8;
+                    for (int j2 : E.msub[m2]) {
+                        if (j2 < 0) continue;
+                        ZOut out;
+                        out.zoff = zrow + E.sub[j2].off;
+                        out.ldz = NE2x;
+                        out.M = dS;
+                        out.N = E.sub[j2].dim;
+                        for (auto& f : fd[E.sub[j2].sigma]) {
+                            const Blk& bb = Bo->blk[f.second];
+                            const int j = f.first;
+                            out.chunks.push_back(GemmChunk{1.0, B.poff[x] + E.sub[j].off, bb.off, ldx, bb.cols,
+                                                           E.sub[j].dim, 2, 1, 0, (uint8_t)!tm.tb});
+                        }
+                        w.z.push_back(std::move(out));
+                    }
+                    zrow_done = true;
+                }
+            }
             for (int i : S.msub[mS]) {
                 if (i < 0) continue;
                 const int di = S.sub[i].dim;
@@ -1501,24 +1546,32 @@ dmrg_status Engine::build_heff_plan(Bond& B) {
                         }
                     continue;
                 }
-                // Z_t[x, i]: d_i x NE2, sub-sector j2 at its column offset
+                // Z_t[x, i]: d_i x NE2, sub-sector j2 at its column offset (rows of
+                // several i of one block are contiguous when they share a Z, below)
+                int64_t zo;
+                if (zrow_done) {
+                    zo = zrow + (int64_t)S.sub[i].off * NE2x;
+                } else {
+                    zo = w.zsize;
+                    w.zsize += ((int64_t)di * E.md[mE2] + 7) / 8 * 8;
+                }
                 const int NE2 = E.md[mE2];
-                const int64_t zo = w.zsize;
-                w.zsize += ((int64_t)di * NE2 + 7) / 8 * 8;
-                for (int j2 : E.msub[mE2]) {
-                    if (j2 < 0) continue;
-                    ZOut out;
-                    out.zoff = zo + E.sub[j2].off;
-                    out.ldz = NE2;
-                    out.M = di;
-                    out.N = E.sub[j2].dim;
-                    for (auto& f : feeds[E.sub[j2].sigma]) {
-                        const Blk& bb = Bo->blk[f.second];
-                        const int j = f.first;
-                        out.chunks.push_back(GemmChunk{1.0, xrow + E.sub[j].off, bb.off, ldx, bb.cols, E.sub[j].dim, 2,
-                                                       1, 0, (uint8_t)!tm.tb});
+                if (!zrow_done) {
+                    for (int j2 : E.msub[mE2]) {
+                        if (j2 < 0) continue;
+                        ZOut out;
+                        out.zoff = zo + E.sub[j2].off;
+                        out.ldz = NE2;
+                        out.M = di;
+                        out.N = E.sub[j2].dim;
+                        for (auto& f : feeds[E.sub[j2].sigma]) {
+                            const Blk& bb = Bo->blk[f.second];
+                            const int j = f.first;
+                            out.chunks.push_back(GemmChunk{1.0, xrow + E.sub[j].off, bb.off, ldx, bb.cols,
+                                                           E.sub[j].dim, 2, 1, 0, (uint8_t)!tm.tb});
+                        }
+                        w.z.push_back(std::move(out));   // no chunks: the columns are cleared
                     }
-                    w.z.push_back(std::move(out));   // no chunks: the columns are cleared
                 }
                 for (int ai : A->acting(i, tm.ta)) {
                     const Blk& ab = A->blk[ai];
