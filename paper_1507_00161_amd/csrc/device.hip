@@ -302,15 +302,15 @@ constexpr int kOutside = 0x7fffff80;   // an offset past the range
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base) {
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, kRecords, 0x00020000);
 }
-template <class T> __device__ __forceinline__ T bload(__amdgpu_buffer_rsrc_t r, int off);
-template <> __device__ __forceinline__ float bload<float>(__amdgpu_buffer_rsrc_t r, int off) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+template <class T> __device__ __forceinline__ T bload(__amdgpu_buffer_rsrc_t r, int voff, int soff);
+template <> __device__ __forceinline__ float bload<float>(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
 }
-template <> __device__ __forceinline__ double bload<double>(__amdgpu_buffer_rsrc_t r, int off) {
-    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+template <> __device__ __forceinline__ double bload<double>(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
 }
-template <> __device__ __forceinline__ bf16_t bload<bf16_t>(__amdgpu_buffer_rsrc_t r, int off) {
-    return __builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0);
+template <> __device__ __forceinline__ bf16_t bload<bf16_t>(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+    return __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0);
 }
 // scaled value for the LDS store (BF16: scaled in FP32, rounded back)
 template <class T, class S> __device__ __forceinline__ T scaled(T v, S s) { return v * s; }
@@ -327,36 +327,36 @@ struct Slice {
     typedef typename MmaTraits<T>::scale_t S;
     T v[E];
     S scale;
-    // element (r, k) at P[r*ld + k]: lane -> k = t % BK, rows t / BK + (256 / BK) u
-    __device__ __forceinline__ void load_k(const T* P, int ld, int r0, int rmax, int k0, int K, S s, int tid) {
+    // Global loads of one slice.  Element (r, k) lies at P[r*ld + k] ("along
+    // K": lane -> k = t % BK, rows t / BK + RS u) or at P[k*ld + r] ("along
+    // M/N": lane -> r = t % 16 + 16 (t / 64), k = (t / 16) % 4 + 4 u; 16
+    // consecutive r per row for coalescing, and a wave's LDS stores then fall
+    // in 64 different banks).  Both layouts reduce to per-element byte offsets
+    // base + u step for u below a count nv, so one set of loads serves both:
+    // the staged values sit in the same registers whatever a chunk's layout,
+    // and nothing forces the loads of one slice to complete before the MFMAs
+    // of the previous one.
+    __device__ __forceinline__ void load(const T* P, bool along_k, int ld, int r0, int rmax, int k0, int K, S s,
+                                         int tid) {
         constexpr int RS = NTH / BK;
-        const int k = tid % BK, r = tid / BK;
-        const bool kin = k0 + k < K;
+        constexpr int SH = RS == 8 ? 3 : (RS == 16 ? 4 : 5);
+        static_assert((1 << SH) == RS, "rows per pass must be 8, 16 or 32");
+        int base, step, nv;
+        if (along_k) {
+            const int k = tid % BK, r = tid / BK;
+            base = ((r0 + r) * ld + k0 + k) * (int)sizeof(T);
+            step = RS * ld * (int)sizeof(T);
+            nv = k0 + k < K ? (rmax - r + RS - 1) >> SH : 0;
+        } else {
+            const int r = (tid & 15) + 16 * (tid >> 6), k = (tid >> 4) & 3;
+            base = ((k0 + k) * ld + r0 + r) * (int)sizeof(T);
+            step = 4 * ld * (int)sizeof(T);
+            nv = r < rmax ? (K - k0 - k + 3) >> 2 : 0;
+        }
         const __amdgpu_buffer_rsrc_t rs = make_rsrc(P);
-        const int base = ((r0 + r) * ld + k0 + k) * (int)sizeof(T);
-        const int step = RS * ld * (int)sizeof(T);
         scale = s;
 #pragma unroll
-        for (int u = 0; u < E; ++u) {
-            const bool in = kin && r + RS * u < rmax;
-            v[u] = bload<T>(rs, in ? base + u * step : kOutside);
-        }
-    }
-    // element (r, k) at P[k*ld + r]: lane -> r = t % 16 + 16 (t / 64), k = (t / 16) % 4 + 4 u
-    // (16 consecutive r per row for coalescing; a wave's LDS stores then fall
-    // in 64 different banks)
-    __device__ __forceinline__ void load_m(const T* P, int ld, int r0, int rmax, int k0, int K, S s, int tid) {
-        const int r = (tid & 15) + 16 * (tid >> 6), k = (tid >> 4) & 3;
-        const bool rin = r < rmax;
-        const __amdgpu_buffer_rsrc_t rs = make_rsrc(P);
-        const int base = ((k0 + k) * ld + r0 + r) * (int)sizeof(T);
-        const int step = 4 * ld * (int)sizeof(T);
-        scale = s;
-#pragma unroll
-        for (int u = 0; u < E; ++u) {
-            const bool in = rin && k0 + k + 4 * u < K;
-            v[u] = bload<T>(rs, in ? base + u * step : kOutside);
-        }
+        for (int u = 0; u < E; ++u) v[u] = bload<T>(rs, u < nv ? base + u * step : kOutside, 0);
     }
     __device__ __forceinline__ void store_k(T* __restrict__ Sm, int tid) const {
         constexpr int RS = NTH / BK;
@@ -386,7 +386,14 @@ __device__ __forceinline__ void gemm_body(const Bufs& bufs, const GemmTask* __re
     __shared__ T As[2][TM * LDK];
     __shared__ T Bs[2][TN * LDK];
     const int tid = threadIdx.x;
-    const int wave = tid >> 6, lane = tid & 63;
+    // The wave index is uniform across a wave.  The FP32 and BF16 bodies keep
+    // it in a scalar register: the quadrant tests below become scalar branches
+    // rather than exec-mask updates, and the next slice's global loads stay in
+    // flight over the MFMAs instead of being waited for at the branch join.
+    // The FP64 body (no such wait) needs the vector registers more and keeps
+    // it per lane.
+    const int wave = sizeof(T) == 8 ? tid >> 6 : __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int lane = tid & 63;
     const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;   // wave quadrant
     const int fr = lane & 15, fk = lane >> 4;
     int ti = sc.wg_off[blockIdx.x];
@@ -402,10 +409,8 @@ __device__ __forceinline__ void gemm_body(const Bufs& bufs, const GemmTask* __re
         const T* B = (const T*)bufs.p[ch.b_buf] + ch.b_off;
         typedef typename MmaTraits<T>::scale_t S;
         const S alpha = (S)ch.alpha;
-        if (!ch.a_trans) ra.load_k(A, ch.lda, t.m0, t.mt, k0, ch.K, alpha, tid);
-        else ra.load_m(A, ch.lda, t.m0, t.mt, k0, ch.K, alpha, tid);
-        if (!ch.b_trans) rb.load_m(B, ch.ldb, t.n0, t.nt, k0, ch.K, S(1), tid);
-        else rb.load_k(B, ch.ldb, t.n0, t.nt, k0, ch.K, S(1), tid);
+        ra.load(A, !ch.a_trans, ch.lda, t.m0, t.mt, k0, ch.K, alpha, tid);
+        rb.load(B, ch.b_trans, ch.ldb, t.n0, t.nt, k0, ch.K, S(1), tid);
     };
     auto store = [&](const GemmChunk& ch, int buf) {
         if (!ch.a_trans) ra.store_k(As[buf], tid);

@@ -318,34 +318,28 @@ static void schedule_tasks(const GB& g, std::vector<GemmTask>& tasks, const std:
                 if (xcd_of[t] >= 0) order[fp[xcd_of[t]]++] = t;
         }
     }
-    // per XCD: each task onto its least-loaded work-group (LPT), or, with many
-    // tasks per work-group, round-robin over the work-groups
+    // per XCD: each task onto its least-loaded work-group.  With few tasks per
+    // work-group the tasks go largest first (LPT); with many, in dealing order
+    // (list scheduling), so that work-groups running at the same time work on
+    // neighbouring tiles, which share operands in the XCD's L2, while the
+    // loads still end within about one task of each other.
     std::vector<int32_t> wg_of(n, -1);
-    if (lpt) {
-        typedef std::pair<double, int> QE;
-        std::vector<QE> heap;
-        auto cmp = [](const QE& a, const QE& b) { return a > b; };   // min-heap on (load, j)
-        for (int x = 0; x < 8; ++x) {
-            auto b = order.begin() + xoff[x], e = order.begin() + xoff[x + 1];
+    typedef std::pair<double, int> QE;
+    std::vector<QE> heap;
+    auto cmp = [](const QE& a, const QE& b) { return a > b; };   // min-heap on (load, j)
+    for (int x = 0; x < 8; ++x) {
+        auto b = order.begin() + xoff[x], e = order.begin() + xoff[x + 1];
+        if (lpt)
             std::sort(b, e, [&](int64_t p, int64_t q) { return cost[p] != cost[q] ? cost[p] > cost[q] : p < q; });
-            heap.clear();
-            for (int j = 0; j < gw; ++j) heap.push_back({0.0, j});
-            std::make_heap(heap.begin(), heap.end(), cmp);
-            for (auto it = b; it != e; ++it) {
-                std::pop_heap(heap.begin(), heap.end(), cmp);
-                QE& q = heap.back();
-                wg_of[*it] = 8 * q.second + x;
-                q.first += cost[*it];
-                std::push_heap(heap.begin(), heap.end(), cmp);
-            }
-        }
-    } else {
-        for (int x = 0; x < 8; ++x) {
-            int j = 0;
-            for (int64_t i = xoff[x]; i < xoff[x + 1]; ++i) {
-                wg_of[order[i]] = 8 * j + x;
-                if (++j == gw) j = 0;
-            }
+        heap.clear();
+        for (int j = 0; j < gw; ++j) heap.push_back({0.0, j});
+        std::make_heap(heap.begin(), heap.end(), cmp);
+        for (auto it = b; it != e; ++it) {
+            std::pop_heap(heap.begin(), heap.end(), cmp);
+            QE& q = heap.back();
+            wg_of[*it] = 8 * q.second + x;
+            q.first += cost[*it];
+            std::push_heap(heap.begin(), heap.end(), cmp);
         }
     }
     // counting sort by work-group; within a work-group, tasks keep dealing order
