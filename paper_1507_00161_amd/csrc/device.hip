@@ -913,32 +913,26 @@ __global__ void __launch_bounds__(64) k_small_eigh(const double* __restrict__ G,
         Vm[i][j] = i == j ? 1.0 : 0.0;
     }
     __syncthreads();
-    // lane -> (row or column i = t % 32, pairs half, half + 2, ...): no
-    // integer division in the inner loops
-    const int li = t & 31, half = t >> 5, npair = kk / 2;
     for (int sweep = 0; sweep < 30 && kk > 1; ++sweep) {
         double off = 0.0, tot = 0.0;
-        if (li < k)
-            for (int r = half; r < k; r += 2) {
-                const double v = A[r][li] * A[r][li];
-                tot += v;
-                if (r != li) off += v;
-            }
+        for (int e = t; e < k * k; e += 64) {
+            int i = e / k, j = e % k;
+            double v = A[i][j] * A[i][j];
+            tot += v;
+            if (i != j) off += v;
+        }
         for (int o = 32; o > 0; o >>= 1) {
             off += __shfl_xor(off, o, 64);
             tot += __shfl_xor(tot, o, 64);
         }
         if (off <= 1e-28 * tot || off < 1e-300) break;
         for (int round = 0; round < kk - 1; ++round) {
-            if (t < npair) {
+            if (t < kk / 2) {
                 const int i1 = t, i2 = kk - 1 - t;
-                int x1 = i1 - 1 + round, x2 = i2 - 1 + round;   // both < 2 (kk - 1)
-                if (x1 >= kk - 1) x1 -= kk - 1;
-                if (x2 >= kk - 1) x2 -= kk - 1;
-                int p = i1 == 0 ? 0 : 1 + x1;
-                int q = 1 + x2;
+                int p = i1 == 0 ? 0 : 1 + (i1 - 1 + round) % (kk - 1);
+                int q = 1 + (i2 - 1 + round) % (kk - 1);
                 if (p > q) {
-                    const int x = p;
+                    int x = p;
                     p = q;
                     q = x;
                 }
@@ -946,10 +940,10 @@ __global__ void __launch_bounds__(64) k_small_eigh(const double* __restrict__ G,
                 pr[t][1] = q;
                 double c = 1.0, sn = 0.0;
                 if (q < k) {
-                    const double apq = A[p][q];
+                    double apq = A[p][q];
                     if (fabs(apq) > 1e-300) {
-                        const double th = (A[q][q] - A[p][p]) / (2.0 * apq);
-                        const double tt = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+                        double th = (A[q][q] - A[p][p]) / (2.0 * apq);
+                        double tt = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
                         c = 1.0 / sqrt(tt * tt + 1.0);
                         sn = tt * c;
                     }
@@ -958,28 +952,28 @@ __global__ void __launch_bounds__(64) k_small_eigh(const double* __restrict__ G,
                 cs[t][1] = sn;
             }
             __syncthreads();
-            if (li < k)   // columns p, q of A and V, row li
-                for (int pi = half; pi < npair; pi += 2) {
-                    const int p = pr[pi][0], q = pr[pi][1];
-                    if (q >= k) continue;
-                    const double c = cs[pi][0], sn = cs[pi][1];
-                    const double aip = A[li][p], aiq = A[li][q];
-                    A[li][p] = c * aip - sn * aiq;
-                    A[li][q] = sn * aip + c * aiq;
-                    const double vip = Vm[li][p], viq = Vm[li][q];
-                    Vm[li][p] = c * vip - sn * viq;
-                    Vm[li][q] = sn * vip + c * viq;
-                }
+            for (int e = t; e < (kk / 2) * k; e += 64) {
+                int pi = e / k, i = e % k;
+                int p = pr[pi][0], q = pr[pi][1];
+                if (q >= k) continue;
+                double c = cs[pi][0], sn = cs[pi][1];
+                double aip = A[i][p], aiq = A[i][q];
+                A[i][p] = c * aip - sn * aiq;
+                A[i][q] = sn * aip + c * aiq;
+                double vip = Vm[i][p], viq = Vm[i][q];
+                Vm[i][p] = c * vip - sn * viq;
+                Vm[i][q] = sn * vip + c * viq;
+            }
             __syncthreads();
-            if (li < k)   // rows p, q of A, column li
-                for (int pi = half; pi < npair; pi += 2) {
-                    const int p = pr[pi][0], q = pr[pi][1];
-                    if (q >= k) continue;
-                    const double c = cs[pi][0], sn = cs[pi][1];
-                    const double apj = A[p][li], aqj = A[q][li];
-                    A[p][li] = c * apj - sn * aqj;
-                    A[q][li] = sn * apj + c * aqj;
-                }
+            for (int e = t; e < (kk / 2) * k; e += 64) {
+                int pi = e / k, j = e % k;
+                int p = pr[pi][0], q = pr[pi][1];
+                if (q >= k) continue;
+                double c = cs[pi][0], sn = cs[pi][1];
+                double apj = A[p][j], aqj = A[q][j];
+                A[p][j] = c * apj - sn * aqj;
+                A[q][j] = sn * apj + c * aqj;
+            }
             __syncthreads();
         }
     }
