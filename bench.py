@@ -76,6 +76,42 @@ def run_schedule(workload, prec: str, warmup: int, steps: int, D_main: int, seed
     return dict(energy=energy, walls=walls, tot=tot)
 
 
+def plateaus(name: str, prec: str, Ds, per: int, tol: float):
+    """Energy against discarded weight along a D schedule of plateaus (`per`
+    sweeps at each D), with the sweep time and the H_eff GEMM throughput of the
+    last sweep of each plateau; one JSON line per plateau."""
+    import torch
+    import paper_1507_00161_amd as pk
+    from workloads import WORKLOADS
+    h = WORKLOADS[name].hamiltonian()
+    sp = h.space
+    ctx = pk.Context(precision=PREC[prec], davidson_tol=tol, noise=1e-4, noise_sweeps=2, seed=1507)
+    ctx.load_hamiltonian(sp.species, sp.two_m, h.eps, h.V.ravel(), h.n_p, h.n_n, h.two_M)
+    peak = PEAK[prec]
+    for D in Ds:
+        for k in range(per):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            r = ctx.sweep(D)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t
+            log(f"[{name} {prec}] D={D} sweep {k}: E={r['energy']:.9f} discarded max {r['discarded_max']:.2e} "
+                f"{wall:.1f}s products lo/64={r['products_low']}/{r['products_fp64']}")
+        free, total = torch.cuda.mem_get_info()
+        g = {}
+        for ph, kn in (("gemm1", "k_heff_z"), ("gemm2", "k_heff_y")):
+            if r[f"{ph}_seconds"] > 0:
+                tf = r[f"{ph}_flops"] / r[f"{ph}_seconds"] / 1e12
+                g[kn] = {"tflops": tf, "frac_of_peak": tf / peak}
+        print(json.dumps({"workload": name, "precision": prec, "D": D, "energy": r["energy"],
+                          "discarded_max": r["discarded_max"], "discarded_sum": r["discarded_sum"],
+                          "sweep_s": wall, "heff_tflops": r["heff_flops"] / max(r["heff_seconds"], 1e-12) / 1e12,
+                          "products_low": r["products_low"], "products_fp64": r["products_fp64"],
+                          "not_converged": r["not_converged"], "gemm_phases": g,
+                          "device_mem_used_gb": (total - free) / 1e9}), flush=True)
+    ctx.close()
+
+
 def cpu_baseline(budget_s: float = 20.0):
     """The oracle's own H_eff.psi throughput on a bounded sample of the same
     workload: its first sweep at D = 64, stopped after `budget_s` seconds."""
@@ -286,6 +322,10 @@ def main():
     ap.add_argument("--bench-json", help="the benchmark line of the profiled run")
     ap.add_argument("--kernel", help="kernel to summarise (default: the benchmark line's roofline kernel)")
     ap.add_argument("--copy-reference", type=int, metavar="MIB", help="one plain device copy of MIB MiB")
+    ap.add_argument("--plateaus", metavar="WORKLOAD",
+                    help="energy vs discarded weight along --D-list plateaus (--per sweeps each)")
+    ap.add_argument("--D-list", default="512,1024,2048")
+    ap.add_argument("--per", type=int, default=2)
     ap.add_argument("--batched", type=int, metavar="K",
                     help="independent small solves: K instances one at a time vs dmrg_sweep_many")
     args = ap.parse_args()
@@ -300,6 +340,10 @@ def main():
         return
     if args.batched:
         batched(args.batched)
+        return
+    if args.plateaus:
+        for p in [x.strip() for x in args.precisions.split(",") if x.strip()]:
+            plateaus(args.plateaus, p, [int(x) for x in args.D_list.split(",")], args.per, args.tol)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs one GPU; the multi-GPU path (term-sharded H_eff with an "
