@@ -300,8 +300,10 @@ def batched(k: int, precision: str = "fp32"):
     for c in ctxs:
         c.close()
     diff = max(abs(o["energy"] - e) / abs(e) for o, e in zip(out, e_seq))
+    flops = sum(o["heff_flops"] for o in out)
     res = {"batched": {"instances": k, "precision": precision, "status": st,
                        "sequential_s": t_seq, "concurrent_s": t_con, "speedup": t_seq / t_con,
+                       "heff_gflop_total": flops / 1e9, "heff_tflops_over_wall": flops / t_con / 1e12,
                        "max_rel_energy_diff": diff,
                        "spaces": [w.space for w in ws], "D": [w.D_schedule[0] for w in ws]}}
     print(json.dumps(res))
