@@ -161,6 +161,22 @@ def vacuum(side: str, lo: int) -> Block:
     return b
 
 
+def dbss_count(w_desc, D: int, eps: float, d_min: int) -> int:
+    """Dynamic block-state selection (DBSS).  The paper's block-state
+    paragraph (the method description after Eq. 1) has the number of block
+    states set by an a priori truncation error delta eps_TR, with a minimum
+    M_min in the production runs; the rule itself is only cited.  Reading: keep the fewest largest
+    weights (w_desc, descending) whose discarded remainder 1 - sum(kept) is
+    at most eps, then clamp to [d_min, D].  The remainder is formed by adding
+    the weights in descending order.  The caller applies its tie rule to the
+    count afterwards."""
+    n, kept = 0, 0.0
+    while n < len(w_desc) and 1.0 - kept > eps:
+        kept += w_desc[n]
+        n += 1
+    return min(max(n, d_min), D, len(w_desc))
+
+
 @dataclasses.dataclass
 class Options:
     davidson_tol: float = 1e-7
@@ -171,6 +187,8 @@ class Options:
     select_basis: bool = False   # truncate by configuration selection (tests)
     noise: float = 0.0           # density-matrix perturbation weight alpha ...
     noise_sweeps: int = 0        # ... applied during the first noise_sweeps sweeps
+    trunc_eps: float = 0.0       # > 0: dynamic block-state selection (DBSS) to this truncation error
+    d_min: int = 0               # DBSS: fewest block states kept (D is the most)
 
 
 @dataclasses.dataclass
@@ -736,6 +754,9 @@ class DMRG:
             iso[q] = U
         return iso
 
+    def dbss_count(self, w_desc, D: int) -> int:
+        return dbss_count(w_desc, D, self.opts.trunc_eps, self.opts.d_min)
+
     def density_iso(self, rho: Dict[QN, np.ndarray], D: int):
         """Keep the D largest density-matrix weights over all sectors.
 
@@ -754,6 +775,8 @@ class DMRG:
                 allw.append((float(w[x]), q, x))
         allw.sort(key=lambda t: -t[0])
         n = min(D, len(allw))
+        if o.trunc_eps > 0.0:
+            n = self.dbss_count([t[0] for t in allw], D)
         n0 = n
         while 0 < n < len(allw) and allw[n - 1][0] - allw[n][0] <= o.tie_tol:
             n -= 1
@@ -1017,6 +1040,7 @@ class DMRG:
         if not self.R:
             self.initialize(D)
         thetas, disc_max, nprod0 = [], 0.0, self.nprod_total
+        kept_max = 0
         alpha = self.opts.noise if self.sweeps_done < self.opts.noise_sweeps else 0.0
         setup = None
         for bond in range(0, N - 1):
@@ -1036,6 +1060,7 @@ class DMRG:
             else:
                 iso, disc = self.density_iso(self.rho_left(self.psi, Sops, alpha, bond), D)
             disc_max = max(disc_max, disc)
+            kept_max = max(kept_max, sum(U.shape[1] for U in iso.values()))
             Lnew = self.new_block("L", 0, bond + 1, enlL, Sops, iso, self.L[bond])
             self.L[bond + 1] = Lnew
             nsetup = self.setup_bond(bond + 1)
@@ -1059,6 +1084,7 @@ class DMRG:
             else:
                 iso, disc = self.density_iso(self.rho_right(self.psi, Eops, alpha, bond), D)
             disc_max = max(disc_max, disc)
+            kept_max = max(kept_max, sum(U.shape[1] for U in iso.values()))
             Rnew = self.new_block("R", bond + 1, N, enlR, Eops, iso, self.R[bond + 2])
             self.R[bond + 1] = Rnew
             nsetup = self.setup_bond(bond - 1)
@@ -1067,7 +1093,7 @@ class DMRG:
             setup = nsetup
         self.sweeps_done += 1
         return dict(energy=min(thetas), last=self.theta, discarded_max=disc_max,
-                    nprod=self.nprod_total - nprod0)
+                    nprod=self.nprod_total - nprod0, kept_max=kept_max)
 
     # ------------------------------------------------------------ helpers
     def psi_configs(self, enlL: Enlarged, enlR: Enlarged):

@@ -33,6 +33,9 @@ CASES = [
     # pf + g9/2 (60 sites, 12p + 12n, the 64Ge-sized space), J_z = 0 and J_z = 2
     ("pfg9_12p12n_D16", "pfg9_12p12n", None, [16, 16]),
     ("pfg9_12p12n_M2_D16", "pfg9_12p12n_M2", None, [16]),
+    # dynamic block-state selection: the kept count follows the truncation error
+    ("p_2p2n_dbss", "p_2p2n", None, [64, 64, 64], {"trunc_eps": 1e-6, "d_min": 4}),
+    ("sd_4p4n_dbss", "sd_4p4n", None, [128, 128, 128], {"trunc_eps": 1e-3, "d_min": 8}),
 ]
 
 
@@ -45,15 +48,18 @@ def hamiltonian(spec):
 
 def main():
     out = {"options": OPTS, "cases": {}}
-    for name, spec, oseed, sched in CASES:
+    for name, spec, oseed, sched, *extra in CASES:
+        extra = extra[0] if extra else {}
         h = hamiltonian(spec)
         sp = h.space
         order = None if oseed is None else random_ordering(sp.n_sites, oseed)
         t = time.time()
         o = dmrg.DMRG(h.eps, h.V, sp.species, sp.two_m, h.n_p, h.n_n, h.two_M, order,
-                      dmrg.Options(**OPTS))
-        energies = [o.sweep(D)["energy"] for D in sched]
+                      dmrg.Options(**OPTS, **extra))
+        res = [o.sweep(D) for D in sched]
+        energies = [r["energy"] for r in res]
         case = {"workload": spec, "ordering_seed": oseed, "D": sched, "energies": energies,
+                "kept_max": [r["kept_max"] for r in res], "options": extra,
                 "target": [h.n_p, h.n_n, h.two_M]}
         if sp.n_sites <= 24:
             case["exact"] = float(ed.ground_energy(h.eps, h.V, sp.species, sp.two_m,

@@ -7,7 +7,8 @@
 * closed forms: the degenerate pairing model, V = 0, two particles;
 * the DMRG projection identity H_eff = P^T H P with P a selection of
   determinants, checked element by element against Slater-Condon rules;
-* DMRG at a bond dimension that holds the exact state equals ED.
+* DMRG at a bond dimension that holds the exact state equals ED;
+* the dynamic block-state count against a search over its definition.
 """
 import itertools
 import math
@@ -285,3 +286,57 @@ def test_dmrg_projection_identity_selected_basis(name, n_p, n_n, two_M, D):
     assert len(seen) == 4 * (space.n_sites - 1)
     # truncation really happened somewhere
     assert any(sum(b.dims.values()) == D for b in o.L.values())
+
+
+# ------------------------------------------ dynamic block-state selection
+def test_dbss_count_against_search():
+    """The DBSS count against its definition by search: the smallest n whose
+    discarded weight (1 - the fresh sum of the n largest weights) is at most
+    eps, then clamped to [d_min, D], on random weight spectra."""
+    rng = np.random.default_rng(5)
+    checked = 0
+    for _ in range(300):
+        w = np.sort(rng.dirichlet(np.full(int(rng.integers(1, 40)), 0.3)))[::-1]
+        eps = float(10.0 ** rng.uniform(-8, -0.3))
+        d_min, D = int(rng.integers(0, 6)), int(rng.integers(1, 50))
+        disc = [1.0 - math.fsum(w[:n]) for n in range(len(w) + 1)]
+        if any(abs(d - eps) < 1e-12 for d in disc):
+            continue                                    # a rounding tie at the threshold
+        n = next(n for n in range(len(w) + 1) if disc[n] <= eps)
+        assert dmrg.dbss_count(list(w), D, eps, d_min) == min(max(n, d_min), D, len(w))
+        checked += 1
+    assert checked > 250
+
+
+def test_dbss_truncations_meet_the_error():
+    """Along a DBSS run every truncation keeps D states or discards at most
+    eps, and the count moves with eps (fewer states for a looser error)."""
+    h = WORKLOADS["sd_4p4n"].hamiltonian()
+    sp_ = h.space
+
+    class Rec(dmrg.DMRG):
+        def density_iso(self, rho, D):
+            iso, disc = super().density_iso(rho, D)
+            self.log.append((sum(U.shape[1] for U in iso.values()), disc, D))
+            return iso, disc
+
+    kept = {}
+    for eps in (1e-2, 1e-3):
+        o = Rec(h.eps, h.V, sp_.species, sp_.two_m, h.n_p, h.n_n, h.two_M, None,
+                dmrg.Options(davidson_tol=1e-8, noise=1e-4, noise_sweeps=1, seed=7, trunc_eps=eps, d_min=4))
+        o.log = []
+        for _ in range(2):
+            o.sweep(96)
+        assert o.log and all(d <= eps + 1e-12 or n == D for n, d, D in o.log)
+        kept[eps] = sum(n for n, _, _ in o.log)
+    assert kept[1e-2] < kept[1e-3]
+
+
+def test_dbss_exact_at_full_rank():
+    """With a bond dimension above the exact Schmidt rank and a tiny error,
+    DBSS reproduces exact diagonalisation."""
+    h = WORKLOADS["p_2p2n"].hamiltonian()
+    e0 = ed.ground_energy(h.eps, h.V, h.space.species, h.space.two_m, 2, 2, 0)[0]
+    o, res = _dmrg(h, 64, 3, trunc_eps=1e-10, d_min=1)
+    assert abs(res[-1]["energy"] - e0) < 1e-10
+    assert res[-1]["discarded_max"] <= 1e-10
