@@ -59,6 +59,14 @@ typedef struct dmrg_options {
     void* stream;                  /* hipStream_t to use, NULL = context-owned stream */
     uint64_t mem_cap_bytes;        /* 0 = no cap; else device bytes the context may hold */
     uint64_t scratch_bytes;        /* 0 = automatic; else cap on H_eff intermediate buffers */
+    /* Dynamic block-state selection (DBSS, the paper's block-state paragraph
+     * after Eq. 1): with trunc_eps > 0 each truncation keeps the fewest
+     * largest density-matrix weights whose discarded remainder
+     * 1 - sum(kept), summed in descending order, is at most trunc_eps, and
+     * then at least d_min and at most the sweep's D states; the tie rule
+     * applies to that count.  trunc_eps = 0 (default): D states. */
+    double trunc_eps;              /* default 0; must be >= 0 */
+    int32_t d_min;                 /* default 0; must be >= 0 */
 } dmrg_options;
 
 typedef struct dmrg_sweep_stats {
@@ -95,6 +103,7 @@ typedef struct dmrg_sweep_stats {
     double gemm1_flops, gemm2_flops;
     double gemm1_bytes, gemm2_bytes;   /* algorithmic operand + result bytes */
     double reduce_seconds;             /* split-K reductions of those launches */
+    int64_t kept_max;                  /* most block states kept by a truncation of the sweep */
 } dmrg_sweep_stats;
 
 typedef struct dmrg_ctx dmrg_ctx;

@@ -59,6 +59,8 @@ void dmrg_default_options(dmrg_options* o) {
     o->stream = nullptr;
     o->mem_cap_bytes = 0;
     o->scratch_bytes = 0;
+    o->trunc_eps = 0.0;
+    o->d_min = 0;
 }
 
 dmrg_status dmrg_create(const dmrg_options* opt, dmrg_ctx** out) {
@@ -68,7 +70,8 @@ dmrg_status dmrg_create(const dmrg_options* opt, dmrg_ctx** out) {
     dmrg_default_options(&o);
     if (opt) o = *opt;
     if (o.precision < 0 || o.precision > 2 || o.davidson_tol <= 0 || o.davidson_max_iter < 1 ||
-        o.davidson_max_subspace < 2 || o.davidson_max_subspace > 32 || o.noise < 0 || o.tie_tol < 0) {
+        o.davidson_max_subspace < 2 || o.davidson_max_subspace > 32 || o.noise < 0 || o.tie_tol < 0 ||
+        !(o.trunc_eps >= 0) || o.d_min < 0) {
         g_create_err = "invalid option value";
         return DMRG_ERR_ARG;
     }

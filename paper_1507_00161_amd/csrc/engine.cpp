@@ -2317,7 +2317,16 @@ dmrg_status Engine::truncate_and_move(int D, double alpha, double* disc) {
             for (int e = 0; e < rdim[x]; ++e) all.push_back({hw[woff[x] + e] / tr, x, e});
         std::stable_sort(all.begin(), all.end(), [](const Wt& a, const Wt& c) { return a.w > c.w; });
         int64_t cnt = (int64_t)all.size();
-        int64_t nk = std::min<int64_t>(D, cnt), n0 = nk;
+        int64_t nk = std::min<int64_t>(D, cnt);
+        if (opt_.trunc_eps > 0.0) {
+            // DBSS: the fewest weights whose discarded remainder is at most
+            // trunc_eps (summed in descending order), within [d_min, D]
+            int64_t n = 0;
+            double kw = 0.0;
+            while (n < cnt && 1.0 - kw > opt_.trunc_eps) kw += all[n++].w;
+            nk = std::min<int64_t>(std::min<int64_t>(std::max<int64_t>(n, opt_.d_min), D), cnt);
+        }
+        const int64_t n0 = nk;
         while (nk > 0 && nk < cnt && all[nk - 1].w - all[nk].w <= opt_.tie_tol) --nk;
         if (nk == 0) {
             nk = n0;
@@ -2356,10 +2365,13 @@ dmrg_status Engine::truncate_and_move(int D, double alpha, double* disc) {
         }
         acc_.eig_seconds += now() - td;
     }
+    int64_t kept_tot = 0;
     for (size_t y = 0; y < keep_m.size(); ++y) {
         blk->basis.add(en.mq[keep_m[y]], kdim[y]);
         blk->comp_m.push_back(keep_m[y]);
+        kept_tot += kdim[y];
     }
+    acc_.kept_max = std::max<int64_t>(acc_.kept_max, kept_tot);
     blk->iso_off = iso_off;
     blk->comp = en;
     bool normal_in = left ? normal_S(b) : !normal_S(b);

@@ -85,6 +85,13 @@ def test_calls_out_of_order_and_bad_arguments(pk):
     assert e.value.status == -4
 
 
+def test_invalid_truncation_options_rejected(pk):
+    for kw in ({"trunc_eps": -1e-6}, {"d_min": -1}):
+        with pytest.raises(pk.DMRGError) as e:
+            pk.Context(**kw)
+        assert e.value.status == -1
+
+
 def test_not_converged_warning_keeps_valid_results(pk):
     h = _h()
     c = pk.Context(davidson_max_iter=1)

@@ -153,6 +153,25 @@ def test_sweep_energies_match_oracle(pk, name, precision, rtol):
     assert c.energy() == r["energy"]
 
 
+@pytest.mark.parametrize("name", ["p_2p2n_dbss", "sd_4p4n_dbss"])
+@pytest.mark.parametrize("precision,rtol", [(0, 1e-8), (1, 1e-6)])
+def test_dbss_sweeps_match_oracle(pk, name, precision, rtol):
+    """Dynamic block-state selection (kept count from the truncation error,
+    within [d_min, D]): sweep energies and, in FP64, the largest kept count of
+    each sweep equal the oracle's."""
+    g = _golden()
+    case = g["cases"][name]
+    h = _golden_ham(case["workload"])
+    c = _ctx(pk, h, precision=precision, **g["options"], **case["options"])
+    for D, e_ref, k_ref in zip(case["D"], case["energies"], case["kept_max"]):
+        r = c.sweep(D)
+        assert r["code"] == 0
+        assert abs(r["energy"] - e_ref) <= rtol * abs(e_ref), (D, r["energy"], e_ref)
+        if precision == 0:
+            assert r["kept_max"] == k_ref
+        assert r["discarded_max"] <= case["options"]["trunc_eps"] or r["kept_max"] == D
+
+
 @pytest.mark.parametrize("name", ["pfg9_12p12n", "pfg9_12p12n_M2"])
 def test_pfg9_ramp_lowers_the_energy(pk, name):
     """The 60-site pf + g9/2 space (12p + 12n, J_z = 0 and 2) on a short ramp
