@@ -6,7 +6,8 @@ What it follows:
 * the two-site superblock Xi(l) (x) Lambda (x) Lambda (x) Xi(r) on an ordered
   chain, basis truncation through the Schmidt (SVD) decomposition of the
   superblock state, sweeping left-to-right and back, a fixed number of block
-  states M (called D here) per sweep.
+  states M (called D here) per sweep, or dynamic block-state
+  selection (DBSS) from a truncation error.
 Below that level of detail the paper only cites the standard method; the
 readings taken are: complementary operators for the two-body term (the
 S|E split below), a Davidson eigensolver, density-matrix truncation with a
