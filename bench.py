@@ -76,7 +76,7 @@ def run_schedule(workload, prec: str, warmup: int, steps: int, D_main: int, seed
     return dict(energy=energy, walls=walls, tot=tot)
 
 
-def plateaus(name: str, prec: str, Ds, per: int, tol: float):
+def plateaus(name: str, prec: str, Ds, per: int, tol: float, trunc_eps: float = 0.0, d_min: int = 0):
     """Energy against discarded weight along a D schedule of plateaus (`per`
     sweeps at each D), with the sweep time and the H_eff GEMM throughput of the
     last sweep of each plateau; one JSON line per plateau."""
@@ -85,7 +85,8 @@ def plateaus(name: str, prec: str, Ds, per: int, tol: float):
     from workloads import WORKLOADS
     h = WORKLOADS[name].hamiltonian()
     sp = h.space
-    ctx = pk.Context(precision=PREC[prec], davidson_tol=tol, noise=1e-4, noise_sweeps=2, seed=1507)
+    ctx = pk.Context(precision=PREC[prec], davidson_tol=tol, noise=1e-4, noise_sweeps=2, seed=1507,
+                     trunc_eps=trunc_eps, d_min=d_min)
     ctx.load_hamiltonian(sp.species, sp.two_m, h.eps, h.V.ravel(), h.n_p, h.n_n, h.two_M)
     peak = PEAK[prec]
     for D in Ds:
@@ -96,7 +97,7 @@ def plateaus(name: str, prec: str, Ds, per: int, tol: float):
             torch.cuda.synchronize()
             wall = time.perf_counter() - t
             log(f"[{name} {prec}] D={D} sweep {k}: E={r['energy']:.9f} discarded max {r['discarded_max']:.2e} "
-                f"{wall:.1f}s products lo/64={r['products_low']}/{r['products_fp64']}")
+                f"kept max {r['kept_max']} {wall:.1f}s products lo/64={r['products_low']}/{r['products_fp64']}")
         free, total = torch.cuda.mem_get_info()
         g = {}
         for ph, kn in (("gemm1", "k_heff_z"), ("gemm2", "k_heff_y")):
@@ -104,6 +105,7 @@ def plateaus(name: str, prec: str, Ds, per: int, tol: float):
                 tf = r[f"{ph}_flops"] / r[f"{ph}_seconds"] / 1e12
                 g[kn] = {"tflops": tf, "frac_of_peak": tf / peak}
         print(json.dumps({"workload": name, "precision": prec, "D": D, "energy": r["energy"],
+                          "trunc_eps": trunc_eps, "d_min": d_min, "kept_max": r["kept_max"],
                           "discarded_max": r["discarded_max"], "discarded_sum": r["discarded_sum"],
                           "sweep_s": wall, "heff_tflops": r["heff_flops"] / max(r["heff_seconds"], 1e-12) / 1e12,
                           "products_low": r["products_low"], "products_fp64": r["products_fp64"],
@@ -328,6 +330,8 @@ def main():
                     help="energy vs discarded weight along --D-list plateaus (--per sweeps each)")
     ap.add_argument("--D-list", default="512,1024,2048")
     ap.add_argument("--per", type=int, default=2)
+    ap.add_argument("--trunc-eps", type=float, default=0.0, help="plateaus: DBSS truncation error (0 = fixed D)")
+    ap.add_argument("--d-min", type=int, default=0, help="plateaus: DBSS minimum block states")
     ap.add_argument("--batched", type=int, metavar="K",
                     help="independent small solves: K instances one at a time vs dmrg_sweep_many")
     args = ap.parse_args()
@@ -345,7 +349,8 @@ def main():
         return
     if args.plateaus:
         for p in [x.strip() for x in args.precisions.split(",") if x.strip()]:
-            plateaus(args.plateaus, p, [int(x) for x in args.D_list.split(",")], args.per, args.tol)
+            plateaus(args.plateaus, p, [int(x) for x in args.D_list.split(",")], args.per, args.tol,
+                     args.trunc_eps, args.d_min)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs one GPU; the multi-GPU path (term-sharded H_eff with an "
