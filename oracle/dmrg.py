@@ -7,7 +7,9 @@ What it follows:
   chain, basis truncation through the Schmidt (SVD) decomposition of the
   superblock state, sweeping left-to-right and back, a fixed number of block
   states M (called D here) per sweep, or dynamic block-state
-  selection (DBSS) from a truncation error.
+  selection (DBSS) from a truncation error;
+* the excitation-energy paragraph: the two lowest states targeted at once
+  (n_states = 2), truncated with their averaged density matrix.
 Below that level of detail the paper only cites the standard method; the
 readings taken are: complementary operators for the two-body term (the
 S|E split below), a Davidson eigensolver, density-matrix truncation with a
@@ -190,6 +192,7 @@ class Options:
     noise_sweeps: int = 0        # ... applied during the first noise_sweeps sweeps
     trunc_eps: float = 0.0       # > 0: dynamic block-state selection (DBSS) to this truncation error
     d_min: int = 0               # DBSS: fewest block states kept (D is the most)
+    n_states: int = 1            # 2: the two lowest states, truncated with their averaged density matrix
 
 
 @dataclasses.dataclass
@@ -223,6 +226,8 @@ class DMRG:
         self.L: Dict[int, Block] = {}
         self.R: Dict[int, Block] = {}
         self.psi: Optional[Dict[QN, np.ndarray]] = None
+        self.psi2: Optional[Dict[QN, np.ndarray]] = None   # the second state (n_states = 2)
+        self.theta2 = math.nan
         self.psi_bond: Optional[int] = None
         self.psi_fresh = False     # psi is the converged eigenvector at psi_bond
         self.theta = math.nan
@@ -657,14 +662,25 @@ class DMRG:
                 out[q] += c * v[q]
         return out
 
-    def davidson(self, apply, diag, x0):
+    def davidson(self, apply, diag, x0, lock=None):
         """Lowest eigenpair of the symmetric operator `apply` (Davidson).
 
         Subspace V starts from the normalised guess; the correction is the
         residual divided by (diag - theta), magnitudes below 1e-12 clamped;
         two passes of classical Gram-Schmidt; restart to [x] at the maximum
-        subspace size; converged when ||H x - theta x|| <= tol."""
+        subspace size; converged when ||H x - theta x|| <= tol.  With `lock`
+        (a normalised vector) the search runs in its orthogonal complement:
+        the guess and every correction are orthogonalised against it and the
+        residual is projected, which gives the next eigenpair."""
         o = self.opts
+
+        def deflate(v):
+            if lock is None:
+                return v
+            c = self.vdot(lock, v)
+            return {q: v[q] - c * lock[q] for q in v}
+
+        x0 = deflate(x0)
         nx = math.sqrt(self.vdot(x0, x0))
         x0 = {q: b / nx for q, b in x0.items()}
         Vs, Ws = [x0], [apply(x0)]
@@ -678,7 +694,7 @@ class DMRG:
             theta, s = float(w[0]), U[:, 0]
             x = self.vcomb(s, Vs)
             hx = self.vcomb(s, Ws)
-            r = {q: hx[q] - theta * x[q] for q in x}
+            r = deflate({q: hx[q] - theta * x[q] for q in x})
             rn = math.sqrt(self.vdot(r, r))
             if rn <= o.davidson_tol:
                 converged = True
@@ -697,6 +713,7 @@ class DMRG:
             tn = math.sqrt(self.vdot(t, t))
             t = {q: b / tn for q, b in t.items()}
             for _ in range(2):
+                t = deflate(t)
                 c = [self.vdot(v, t) for v in Vs]
                 proj = self.vcomb(c, Vs)
                 t = {q: t[q] - proj[q] for q in t}
@@ -945,6 +962,7 @@ class DMRG:
             iso = self.selection_iso(enl.dims, D, 1, lo, mix=not self.opts.select_basis)
             self.R[lo] = self.new_block("R", lo, N, enl, ops, iso, Rn)
         self.psi = None
+        self.psi2 = None
         self.psi_bond = 0
         self.psi_fresh = False
 
@@ -1028,6 +1046,18 @@ class DMRG:
         apply = lambda v: self.heff_apply(terms, v)
         theta, x, nprod, conv = self.davidson(apply, diag, guess)
         self.nprod_total += nprod
+        if self.opts.n_states == 2:
+            # the second state: the lowest eigenpair orthogonal to x, from its
+            # own prediction (or the hash-random vector)
+            g2 = self.psi2 if self.psi2 is not None else self.random_psi(layout)
+            c = self.vdot(x, g2)
+            g2 = {q: g2[q] - c * x[q] for q in g2}
+            if math.sqrt(self.vdot(g2, g2)) < 1e-10:
+                g2 = self.random_psi(layout)
+            theta2, x2, nprod2, conv2 = self.davidson(apply, diag, g2, lock=x)
+            self.nprod_total += nprod2
+            self.psi2, self.theta2 = x2, theta2
+            nprod, conv = nprod + nprod2, conv and conv2
         return theta, x, nprod, conv
 
     def sweep(self, D: int, on_step=None) -> dict:
@@ -1041,7 +1071,17 @@ class DMRG:
         if not self.R:
             self.initialize(D)
         thetas, disc_max, nprod0 = [], 0.0, self.nprod_total
+        thetas2 = []
         kept_max = 0
+        two = self.opts.n_states == 2
+
+        def rho_avg(rho_fn, ops, bond):
+            # the two states' density matrices, averaged with equal weights
+            rho = rho_fn(self.psi, ops, alpha, bond)
+            if two:
+                rho2 = rho_fn(self.psi2, ops, alpha, bond)
+                rho = {q: 0.5 * (rho[q] + rho2[q]) for q in rho}
+            return rho
         alpha = self.opts.noise if self.sweeps_done < self.opts.noise_sweeps else 0.0
         setup = None
         for bond in range(0, N - 1):
@@ -1051,6 +1091,7 @@ class DMRG:
                 self.psi, self.theta, self.psi_bond, self.psi_fresh = x, theta, bond, True
                 self.records.append(StepRecord(bond, "LR", theta, nprod, conv, 0.0, 0))
             thetas.append(self.theta)
+            thetas2.append(self.theta2)
             if on_step:
                 on_step(self, bond, "LR", setup)
             if bond == N - 2:
@@ -1059,13 +1100,15 @@ class DMRG:
             if self.opts.select_basis:
                 iso, disc = self.selection_iso(enlL.dims, D, 2, bond + 1), 0.0
             else:
-                iso, disc = self.density_iso(self.rho_left(self.psi, Sops, alpha, bond), D)
+                iso, disc = self.density_iso(rho_avg(self.rho_left, Sops, bond), D)
             disc_max = max(disc_max, disc)
             kept_max = max(kept_max, sum(U.shape[1] for U in iso.values()))
             Lnew = self.new_block("L", 0, bond + 1, enlL, Sops, iso, self.L[bond])
             self.L[bond + 1] = Lnew
             nsetup = self.setup_bond(bond + 1)
             self.psi = self.predict_right(bond, self.psi, enlL, Lnew, enlR, nsetup[0], nsetup[2])
+            if two:
+                self.psi2 = self.predict_right(bond, self.psi2, enlL, Lnew, enlR, nsetup[0], nsetup[2])
             self.psi_bond, self.psi_fresh = bond + 1, False
             setup = nsetup
         for bond in range(N - 2, -1, -1):
@@ -1075,6 +1118,7 @@ class DMRG:
                 self.psi, self.theta, self.psi_bond, self.psi_fresh = x, theta, bond, True
                 self.records.append(StepRecord(bond, "RL", theta, nprod, conv, 0.0, 0))
             thetas.append(self.theta)
+            thetas2.append(self.theta2)
             if on_step:
                 on_step(self, bond, "RL", setup)
             if bond == 0:
@@ -1083,18 +1127,23 @@ class DMRG:
             if self.opts.select_basis:
                 iso, disc = self.selection_iso(enlR.dims, D, 1, bond + 1), 0.0
             else:
-                iso, disc = self.density_iso(self.rho_right(self.psi, Eops, alpha, bond), D)
+                iso, disc = self.density_iso(rho_avg(self.rho_right, Eops, bond), D)
             disc_max = max(disc_max, disc)
             kept_max = max(kept_max, sum(U.shape[1] for U in iso.values()))
             Rnew = self.new_block("R", bond + 1, N, enlR, Eops, iso, self.R[bond + 2])
             self.R[bond + 1] = Rnew
             nsetup = self.setup_bond(bond - 1)
             self.psi = self.predict_left(bond, self.psi, enlR, Rnew, enlL, nsetup[0], nsetup[2])
+            if two:
+                self.psi2 = self.predict_left(bond, self.psi2, enlR, Rnew, enlL, nsetup[0], nsetup[2])
             self.psi_bond, self.psi_fresh = bond - 1, False
             setup = nsetup
         self.sweeps_done += 1
-        return dict(energy=min(thetas), last=self.theta, discarded_max=disc_max,
-                    nprod=self.nprod_total - nprod0, kept_max=kept_max)
+        out = dict(energy=min(thetas), last=self.theta, discarded_max=disc_max,
+                   nprod=self.nprod_total - nprod0, kept_max=kept_max)
+        if two:
+            out["energy_excited"] = min(thetas2)
+        return out
 
     # ------------------------------------------------------------ helpers
     def psi_configs(self, enlL: Enlarged, enlR: Enlarged):

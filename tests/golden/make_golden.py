@@ -36,6 +36,9 @@ CASES = [
     # dynamic block-state selection: the kept count follows the truncation error
     ("p_2p2n_dbss", "p_2p2n", None, [64, 64, 64], {"trunc_eps": 1e-6, "d_min": 4}),
     ("sd_4p4n_dbss", "sd_4p4n", None, [128, 128, 128], {"trunc_eps": 1e-3, "d_min": 8}),
+    # the two lowest states targeted at once (averaged density matrix)
+    ("p_2p2n_two", "p_2p2n", None, [64, 64], {"n_states": 2}),
+    ("sd_4p4n_two", "sd_4p4n", None, [32, 32], {"n_states": 2}),
 ]
 
 
@@ -60,6 +63,7 @@ def main():
         energies = [r["energy"] for r in res]
         case = {"workload": spec, "ordering_seed": oseed, "D": sched, "energies": energies,
                 "kept_max": [r["kept_max"] for r in res], "options": extra,
+                "energies_excited": [r.get("energy_excited") for r in res],
                 "target": [h.n_p, h.n_n, h.two_M]}
         if sp.n_sites <= 24:
             case["exact"] = float(ed.ground_energy(h.eps, h.V, sp.species, sp.two_m,

@@ -340,3 +340,33 @@ def test_dbss_exact_at_full_rank():
     o, res = _dmrg(h, 64, 3, trunc_eps=1e-10, d_min=1)
     assert abs(res[-1]["energy"] - e0) < 1e-10
     assert res[-1]["discarded_max"] <= 1e-10
+
+
+# ------------------------------------------ two lowest states at once
+def test_two_state_exact_bond_dimension_equals_ed():
+    """Targeting the two lowest states with their averaged density matrix:
+    at a bond dimension above the exact Schmidt rank both energies are the
+    two lowest eigenvalues of exact diagonalisation."""
+    h = WORKLOADS["p_2p2n"].hamiltonian()
+    e = ed.ground_energy(h.eps, h.V, h.space.species, h.space.two_m, 2, 2, 0, nroots=2)
+    o, res = _dmrg(h, 64, 2, n_states=2)
+    assert abs(res[-1]["energy"] - e[0]) < 1e-10
+    assert abs(res[-1]["energy_excited"] - e[1]) < 1e-10
+
+
+def test_two_state_energies_are_upper_bounds():
+    """Truncated two-state runs: every step's two Ritz values bound the two
+    lowest exact eigenvalues from above (Hylleraas-Undheim), and more block
+    states never raise the pair."""
+    space = make_space("sd")
+    h = make_hamiltonian(space, 21, 2, 2, 0)
+    e = ed.ground_energy(h.eps, h.V, space.species, space.two_m, 2, 2, 0, nroots=2)
+    last = None
+    for D in (8, 16):
+        o, res = _dmrg(h, D, 3, n_states=2)
+        r = res[-1]
+        assert r["energy"] >= e[0] - 1e-10 and r["energy_excited"] >= e[1] - 1e-10
+        assert r["energy_excited"] >= r["energy"] - 1e-10
+        if last:
+            assert r["energy"] <= last[0] + 1e-8 and r["energy_excited"] <= last[1] + 1e-8
+        last = (r["energy"], r["energy_excited"])
