@@ -67,6 +67,14 @@ typedef struct dmrg_options {
      * applies to that count.  trunc_eps = 0 (default): D states. */
     double trunc_eps;              /* default 0; must be >= 0 */
     int32_t d_min;                 /* default 0; must be >= 0 */
+    /* 1 (default): the ground state.  2: the two lowest states targeted at
+     * once (the paper's excitation-energy paragraph): at each bond the second
+     * state is the lowest eigenpair of H_eff orthogonal to the first (a
+     * Davidson solve in its complement), both are predicted to the next bond,
+     * and the truncation uses their density matrices averaged with equal
+     * weights.  dmrg_energy, dmrg_heff_layout/apply and dmrg_get_psi refer to
+     * the first state; the second state's energy is in the sweep statistics. */
+    int32_t n_states;
 } dmrg_options;
 
 typedef struct dmrg_sweep_stats {
@@ -104,6 +112,7 @@ typedef struct dmrg_sweep_stats {
     double gemm1_bytes, gemm2_bytes;   /* algorithmic operand + result bytes */
     double reduce_seconds;             /* split-K reductions of those launches */
     int64_t kept_max;                  /* most block states kept by a truncation of the sweep */
+    double energy_excited;             /* n_states = 2: lowest step energy of the second state (MeV) */
 } dmrg_sweep_stats;
 
 typedef struct dmrg_ctx dmrg_ctx;

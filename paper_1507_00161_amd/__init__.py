@@ -31,7 +31,7 @@ class Options(ctypes.Structure):
                 ("tie_tol", ctypes.c_double), ("device", ctypes.c_int32),
                 ("stream", ctypes.c_void_p), ("mem_cap_bytes", ctypes.c_uint64),
                 ("scratch_bytes", ctypes.c_uint64), ("trunc_eps", ctypes.c_double),
-                ("d_min", ctypes.c_int32)]
+                ("d_min", ctypes.c_int32), ("n_states", ctypes.c_int32)]
 
 
 class SweepStats(ctypes.Structure):
@@ -49,7 +49,8 @@ class SweepStats(ctypes.Structure):
                 ("gemm1_seconds", ctypes.c_double), ("gemm2_seconds", ctypes.c_double),
                 ("gemm1_flops", ctypes.c_double), ("gemm2_flops", ctypes.c_double),
                 ("gemm1_bytes", ctypes.c_double), ("gemm2_bytes", ctypes.c_double),
-                ("reduce_seconds", ctypes.c_double), ("kept_max", ctypes.c_int64)]
+                ("reduce_seconds", ctypes.c_double), ("kept_max", ctypes.c_int64),
+                ("energy_excited", ctypes.c_double)]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}

@@ -61,6 +61,7 @@ void dmrg_default_options(dmrg_options* o) {
     o->scratch_bytes = 0;
     o->trunc_eps = 0.0;
     o->d_min = 0;
+    o->n_states = 1;
 }
 
 dmrg_status dmrg_create(const dmrg_options* opt, dmrg_ctx** out) {
@@ -71,7 +72,7 @@ dmrg_status dmrg_create(const dmrg_options* opt, dmrg_ctx** out) {
     if (opt) o = *opt;
     if (o.precision < 0 || o.precision > 2 || o.davidson_tol <= 0 || o.davidson_max_iter < 1 ||
         o.davidson_max_subspace < 2 || o.davidson_max_subspace > 32 || o.noise < 0 || o.tie_tol < 0 ||
-        !(o.trunc_eps >= 0) || o.d_min < 0) {
+        !(o.trunc_eps >= 0) || o.d_min < 0 || o.n_states < 1 || o.n_states > 2) {
         g_create_err = "invalid option value";
         return DMRG_ERR_ARG;
     }

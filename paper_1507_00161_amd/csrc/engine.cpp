@@ -589,6 +589,7 @@ dmrg_status Engine::load(int n, const int32_t* species, const int32_t* two_m, co
     L_.clear();
     R_.clear();
     psi_.reset();
+    psi1_.reset();
     init_ = false;
     loaded_ = false;
     have_energy_ = false;
@@ -1819,7 +1820,13 @@ dmrg_status Engine::ensure_dv(int64_t n, int kmax) {
 // product error is second order and the iteration keeps converging.  A solve
 // starts with a refresh (one FP64 product), so a state that is already
 // converged costs a single FP64 product.
-dmrg_status Engine::davidson(Bond& B, double* theta_out, int64_t* nlo, int64_t* n64, bool* conv) {
+//
+// With `lock` (a normalised device vector, the first state) the search runs in
+// its orthogonal complement: the guess and every correction are
+// orthogonalised against it and the residual is projected, which gives the
+// second eigenpair.  `psi` holds the guess on entry and the result on exit.
+dmrg_status Engine::davidson(Bond& B, Buf& psi, const double* lock, double* theta_out, int64_t* nlo,
+                             int64_t* n64, bool* conv) {
     const int64_t n = B.dim;
     const int kmax = std::max(2, std::min(32, opt_.davidson_max_subspace));
     TRY(ensure_dv(n, kmax));
@@ -1839,9 +1846,26 @@ dmrg_status Engine::davidson(Bond& B, double* theta_out, int64_t* nlo, int64_t* 
     *conv = false;
     int refreshes = 0;
     bool exact = true;        // every W column is an FP64 product
+    // v -= (lock . v) lock
+    auto deflate = [&](double* v) -> dmrg_status {
+        if (!lock) return DMRG_OK;
+        DEV(dmrgdev::dots(dev_, lock, 0, 1, v, n, sc + 4));
+        DEV(dmrgdev::combine(dev_, lock, 0, 1, sc + 4, -1.0, n, v, 1));
+        return DMRG_OK;
+    };
+    if (lock) {   // a guess inside the locked direction is replaced by the hash-random start
+        TRY(deflate(psi.d()));
+        DEV(dmrgdev::dots(dev_, psi.d(), 0, 1, psi.d(), n, sc + 3));
+        double g2 = 0.0;
+        DEV(dmrgdev::d2h(dev_, &g2, sc + 3, sizeof(double)));
+        if (!(std::sqrt(std::max(g2, 0.0)) >= 1e-10)) {
+            TRY(random_psi(B, psi));
+            TRY(deflate(psi.d()));
+        }
+    }
     // V0 = psi / |psi|, W0 = H64 V0
-    DEV(dmrgdev::dots(dev_, psi_.d(), 0, 1, psi_.d(), n, sc + 3));
-    DEV(dmrgdev::copy_scaled_inv_norm(dev_, psi_.d(), n, sc + 3, Vm));
+    DEV(dmrgdev::dots(dev_, psi.d(), 0, 1, psi.d(), n, sc + 3));
+    DEV(dmrgdev::copy_scaled_inv_norm(dev_, psi.d(), n, sc + 3, Vm));
     TRY(heff(B, Vm, Wm, dmrgdev::P_F64));
     *n64 += 1;
     int k = 1;
@@ -1857,6 +1881,10 @@ dmrg_status Engine::davidson(Bond& B, double* theta_out, int64_t* nlo, int64_t* 
         DEV(dmrgdev::combine(dev_, Vm, n, k, s, 1.0, n, dv_x_.d(), 0));
         DEV(dmrgdev::combine(dev_, Wm, n, k, s, 1.0, n, dv_hx_.d(), 0));
         DEV(dmrgdev::residual(dev_, dv_hx_.d(), dv_x_.d(), sc, n, dv_r_.d(), sc + 1));
+        if (lock) {   // projected residual
+            TRY(deflate(dv_r_.d()));
+            DEV(dmrgdev::dots(dev_, dv_r_.d(), 0, 1, dv_r_.d(), n, sc + 1));
+        }
         double hs[2];
         DEV(dmrgdev::d2h(dev_, hs, sc, 2 * sizeof(double)));
         theta = hs[0];
@@ -1910,6 +1938,7 @@ dmrg_status Engine::davidson(Bond& B, double* theta_out, int64_t* nlo, int64_t* 
         DEV(dmrgdev::dots(dev_, dv_t_.d(), 0, 1, dv_t_.d(), n, sc + 2));
         DEV(dmrgdev::scale_inv_norm(dev_, dv_t_.d(), n, sc + 2));
         for (int pass = 0; pass < 2; ++pass) {
+            TRY(deflate(dv_t_.d()));
             DEV(dmrgdev::dots(dev_, Vm, n, k, dv_t_.d(), n, cc));
             DEV(dmrgdev::combine(dev_, Vm, n, k, cc, -1.0, n, dv_t_.d(), 1));
         }
@@ -1939,7 +1968,7 @@ dmrg_status Engine::davidson(Bond& B, double* theta_out, int64_t* nlo, int64_t* 
     }
     // psi <- x normalised
     DEV(dmrgdev::dots(dev_, dv_x_.d(), 0, 1, dv_x_.d(), n, sc + 3));
-    DEV(dmrgdev::copy_scaled_inv_norm(dev_, dv_x_.d(), n, sc + 3, psi_.d()));
+    DEV(dmrgdev::copy_scaled_inv_norm(dev_, dv_x_.d(), n, sc + 3, psi.d()));
     *theta_out = theta;
     return DMRG_OK;
 }
@@ -2029,6 +2058,7 @@ std::vector<std::vector<double>> Engine::selection_iso(const std::vector<int>& d
 dmrg_status Engine::initialize(int D) {
     cur_.reset();
     psi_.reset();
+    psi1_.reset();
     L_.clear();
     R_.clear();
     L_.resize(N_ + 1);
@@ -2094,6 +2124,7 @@ dmrg_status Engine::initialize(int D) {
     sweeps_done_ = 0;
     TRY(setup_bond(0, cur_));
     TRY(random_psi(*cur_, psi_));
+    if (opt_.n_states == 2) TRY(random_psi(*cur_, psi1_));
     return DMRG_OK;
 }
 
@@ -2101,8 +2132,8 @@ dmrg_status Engine::initialize(int D) {
 // rho of the S (left = true) or E sectors present in psi, with the
 // perturbation alpha * sum_O (O psi)(O psi)^T over c+ and c of the block's
 // sites.  rho blocks are dense (d x d) at roff[x] for psi block x.
-dmrg_status Engine::density_matrix(Bond& B, bool left, double alpha, Buf& rho, const std::vector<int64_t>& roff,
-                                   const std::vector<int>& rld) {
+dmrg_status Engine::density_matrix(Bond& B, const Buf& psi, double weight, int beta, bool left, double alpha,
+                                   Buf& rho, const std::vector<int64_t>& roff, const std::vector<int>& rld) {
     const Enl &S = B.S, &E = B.E;
     int nb = (int)B.pm_S.size();
     std::vector<int> rdim(nb);
@@ -2113,8 +2144,8 @@ dmrg_status Engine::density_matrix(Bond& B, bool left, double alpha, Buf& rho, c
     int64_t phi = 0;
     for (int x = 0; x < nb; ++x) {
         int ds = S.md[B.pm_S[x]], de = E.md[B.pm_E[x]];
-        if (left) lists[x].push_back(GemmChunk{1.0, B.poff[x], B.poff[x], de, de, de, 0, 0, 0, 1});
-        else lists[x].push_back(GemmChunk{1.0, B.poff[x], B.poff[x], de, de, ds, 0, 0, 1, 0});
+        if (left) lists[x].push_back(GemmChunk{weight, B.poff[x], B.poff[x], de, de, de, 0, 0, 0, 1});
+        else lists[x].push_back(GemmChunk{weight, B.poff[x], B.poff[x], de, de, ds, 0, 0, 1, 0});
     }
     if (alpha != 0.0) {
         const OpSet& ops = left ? B.Sops : B.Eops;
@@ -2166,8 +2197,8 @@ dmrg_status Engine::density_matrix(Bond& B, bool left, double alpha, Buf& rho, c
                         if (left) g1.end(2, po + (int64_t)en.sub[o].off * cols, cols, en.sub[o].dim, cols, 0);
                         else g1.end(2, po + en.sub[o].off, cols, rows, en.sub[o].dim, 0);
                     }
-                    if (left) lists[x2].push_back(GemmChunk{alpha, po, po, cols, cols, cols, 2, 2, 0, 1});
-                    else lists[x2].push_back(GemmChunk{alpha, po, po, cols, cols, rows, 2, 2, 1, 0});
+                    if (left) lists[x2].push_back(GemmChunk{alpha * weight, po, po, cols, cols, cols, 2, 2, 0, 1});
+                    else lists[x2].push_back(GemmChunk{alpha * weight, po, po, cols, cols, rows, 2, 2, 1, 0});
                 }
             }
         }
@@ -2176,7 +2207,7 @@ dmrg_status Engine::density_matrix(Bond& B, bool left, double alpha, Buf& rho, c
     for (int x = 0; x < nb; ++x) {
         g2.begin();
         for (auto& c : lists[x]) g2.chunks.push_back(c);
-        g2.end(3, roff[x], rld[x], rdim[x], rdim[x], 0);
+        g2.end(3, roff[x], rld[x], rdim[x], rdim[x], beta);
     }
     Buf phib;
     TRY(alloc_buf(phib, std::max<int64_t>(phi, 1) * sizeof(double)));
@@ -2184,7 +2215,7 @@ dmrg_status Engine::density_matrix(Bond& B, bool left, double alpha, Buf& rho, c
     TRY(finish_plan(*this, g1, p1));
     TRY(finish_plan(*this, g2, p2));
     const OpSet& ops = left ? B.Sops : B.Eops;
-    BufTable bufs{psi_.p, ops.pool.p, phib.p, rho.p};
+    BufTable bufs{psi.p, ops.pool.p, phib.p, rho.p};
     TRY(run_gemm(dmrgdev::P_F64, bufs, p1));
     TRY(run_gemm(dmrgdev::P_F64, bufs, p2));
     return DMRG_OK;
@@ -2280,7 +2311,12 @@ dmrg_status Engine::truncate_and_move(int D, double alpha, double* disc) {
             DEV(dmrgdev::pad_init(dev_, rho.d() + bk[y][2], (int)bk[y][0], (int)bk[y][1],
                                   nbuf.as<int32_t>() + nlist_off[y]));
         double td = now();
-        TRY(density_matrix(B, left, alpha, rho, roff, rld));
+        if (opt_.n_states == 2) {   // the two states' density matrices, averaged
+            TRY(density_matrix(B, psi_, 0.5, 0, left, alpha, rho, roff, rld));
+            TRY(density_matrix(B, psi1_, 0.5, 1, left, alpha, rho, roff, rld));
+        } else {
+            TRY(density_matrix(B, psi_, 1.0, 0, left, alpha, rho, roff, rld));
+        }
         acc_.density_seconds += now() - td;
         td = now();
         {
@@ -2502,6 +2538,13 @@ dmrg_status Engine::truncate_and_move(int D, double alpha, double* disc) {
     BufTable bufs{psi_.p, nw.iso.p, phib.p, npsi.p, far.iso.p};
     TRY(run_gemm(dmrgdev::P_F64, bufs, p1));
     TRY(run_gemm(dmrgdev::P_F64, bufs, p2));
+    Buf npsi1;   // the second state through the same plans
+    if (opt_.n_states == 2) {
+        TRY(alloc_buf(npsi1, std::max<int64_t>(B2.dim, 1) * sizeof(double)));
+        BufTable bufs1{psi1_.p, nw.iso.p, phib.p, npsi1.p, far.iso.p};
+        TRY(run_gemm(dmrgdev::P_F64, bufs1, p1));
+        TRY(run_gemm(dmrgdev::P_F64, bufs1, p2));
+    }
     // fall back to the hash-random start if the guess vanished
     if (!scal_.p) TRY(alloc_buf(scal_, 64 * sizeof(double)));
     DEV(dmrgdev::dots(dev_, npsi.d(), 0, 1, npsi.d(), B2.dim, scal_.d()));
@@ -2509,6 +2552,7 @@ dmrg_status Engine::truncate_and_move(int D, double alpha, double* disc) {
     DEV(dmrgdev::d2h(dev_, &nn, scal_.p, sizeof(double)));
     psi_ = std::move(npsi);
     if (!(std::sqrt(std::max(nn, 0.0)) >= 1e-10)) TRY(random_psi(B2, psi_));
+    if (opt_.n_states == 2) psi1_ = std::move(npsi1);   // checked when its solve deflates it
     cur_ = std::move(NB);
     acc_.predict_seconds += now() - tpr;
     return DMRG_OK;
@@ -2526,12 +2570,14 @@ dmrg_status Engine::steps(const int32_t* ordering, int D, int64_t max_steps, boo
     if (!init_) {
         TRY(initialize(D));
         sweep_min_ = INFINITY;
+        sweep_min1_ = INFINITY;
         sweep_steps_ = 0;
         acc_ = dmrg_sweep_stats{};
     }
     if (sweep_steps_ == 0) {
         acc_ = dmrg_sweep_stats{};
         sweep_min_ = INFINITY;
+        sweep_min1_ = INFINITY;
     }
     TRY(ensure_dv(cur_->dim, std::max(2, std::min(32, opt_.davidson_max_subspace))));
     dmrg_status ret = DMRG_OK;
@@ -2543,7 +2589,7 @@ dmrg_status Engine::steps(const int32_t* ordering, int D, int64_t max_steps, boo
             int64_t nlo, n64;
             bool conv;
             heff_time_ = 0.0;
-            TRY(davidson(*cur_, &th, &nlo, &n64, &conv));
+            TRY(davidson(*cur_, psi_, nullptr, &th, &nlo, &n64, &conv));
             acc_.heff_seconds += heff_time_;
             acc_.heff_flops += cur_->flops * (double)(nlo + n64);
             acc_.products_low += nlo;
@@ -2554,9 +2600,24 @@ dmrg_status Engine::steps(const int32_t* ordering, int D, int64_t max_steps, boo
                 ret = DMRG_WARN_NOT_CONVERGED;
             }
             theta_ = th;
+            if (opt_.n_states == 2) {   // the second state, in the complement of the first
+                heff_time_ = 0.0;
+                TRY(davidson(*cur_, psi1_, psi_.d(), &th, &nlo, &n64, &conv));
+                acc_.heff_seconds += heff_time_;
+                acc_.heff_flops += cur_->flops * (double)(nlo + n64);
+                acc_.products_low += nlo;
+                acc_.products_fp64 += n64;
+                acc_.solves += 1;
+                if (!conv) {
+                    acc_.not_converged += 1;
+                    ret = DMRG_WARN_NOT_CONVERGED;
+                }
+                theta1_ = th;
+            }
             fresh_ = true;
         }
         sweep_min_ = std::min(sweep_min_, theta_);
+        sweep_min1_ = std::min(sweep_min1_, theta1_);
         ++done;
         ++sweep_steps_;
         acc_.steps += 1;
@@ -2570,6 +2631,7 @@ dmrg_status Engine::steps(const int32_t* ordering, int D, int64_t max_steps, boo
                 have_energy_ = true;
                 energy_ = sweep_min_;
                 acc_.energy = sweep_min_;
+                acc_.energy_excited = opt_.n_states == 2 ? sweep_min1_ : 0.0;
                 acc_.last_theta = theta_;
                 acc_.sweep_seconds = now() - t0;
                 if (st) *st = acc_;
@@ -2577,6 +2639,7 @@ dmrg_status Engine::steps(const int32_t* ordering, int D, int64_t max_steps, boo
                 if (until_sweep_end) return ret;
                 acc_ = dmrg_sweep_stats{};
                 sweep_min_ = INFINITY;
+                sweep_min1_ = INFINITY;
                 t0 = now();
             }
             continue;
@@ -2593,6 +2656,7 @@ dmrg_status Engine::steps(const int32_t* ordering, int D, int64_t max_steps, boo
         TRY(ensure_dv(cur_->dim, std::max(2, std::min(32, opt_.davidson_max_subspace))));
     }
     acc_.energy = sweep_min_;
+    acc_.energy_excited = opt_.n_states == 2 ? sweep_min1_ : 0.0;
     acc_.last_theta = theta_;
     acc_.sweep_seconds += now() - t0;
     if (st) *st = acc_;

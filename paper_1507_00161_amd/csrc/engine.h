@@ -322,10 +322,13 @@ private:
     std::vector<std::unique_ptr<Stored>> L_, R_;
     std::unique_ptr<Bond> cur_;
     Buf psi_;
+    Buf psi1_;                  // the second state (n_states = 2)
     double theta_ = 0.0;
     bool have_energy_ = false;
     double energy_ = 0.0;
     double sweep_min_ = 0.0;
+    double sweep_min1_ = 0.0;   // second state
+    double theta1_ = 0.0;
     int sweep_steps_ = 0;
     dmrg_sweep_stats acc_{};
     // Davidson workspace
@@ -355,9 +358,10 @@ private:
     dmrg_status heff_launch(Bond& B, const double* x, double* y, int prec, bool timed);
     void account(const HeffGroup& g, double es1, double es2);
     dmrg_status ensure_lo(Bond& B, int prec);
-    dmrg_status davidson(Bond& B, double* theta, int64_t* nlo, int64_t* n64, bool* conv);
+    dmrg_status davidson(Bond& B, Buf& psi, const double* lock, double* theta, int64_t* nlo, int64_t* n64,
+                         bool* conv);
     dmrg_status truncate_and_move(int D, double alpha, double* disc);
-    dmrg_status density_matrix(Bond& B, bool left, double alpha, Buf& rho,
+    dmrg_status density_matrix(Bond& B, const Buf& psi, double weight, int beta, bool left, double alpha, Buf& rho,
                                const std::vector<int64_t>& roff, const std::vector<int>& rld);
     dmrg_status random_psi(Bond& B, Buf& out);
     // ev_mid >= 0: record that event between the GEMM and its split-K reduction

@@ -172,6 +172,24 @@ def test_dbss_sweeps_match_oracle(pk, name, precision, rtol):
         assert r["discarded_max"] <= case["options"]["trunc_eps"] or r["kept_max"] == D
 
 
+@pytest.mark.parametrize("name", ["p_2p2n_two", "sd_4p4n_two"])
+@pytest.mark.parametrize("precision,rtol", [(0, 1e-8), (1, 1e-6)])
+def test_two_state_sweeps_match_oracle(pk, name, precision, rtol):
+    """The two lowest states targeted at once: both sweep energies equal the
+    oracle's (and at full rank, p shell, the two lowest ED eigenvalues)."""
+    g = _golden()
+    case = g["cases"][name]
+    h = _golden_ham(case["workload"])
+    c = _ctx(pk, h, precision=precision, **g["options"], **case["options"])
+    for D, e0, e1 in zip(case["D"], case["energies"], case["energies_excited"]):
+        r = c.sweep(D)
+        assert r["code"] == 0
+        assert abs(r["energy"] - e0) <= rtol * abs(e0), (D, r["energy"], e0)
+        assert abs(r["energy_excited"] - e1) <= rtol * abs(e1), (D, r["energy_excited"], e1)
+        assert r["energy_excited"] >= r["energy"]
+    assert c.energy() == r["energy"]
+
+
 @pytest.mark.parametrize("name", ["pfg9_12p12n", "pfg9_12p12n_M2"])
 def test_pfg9_ramp_lowers_the_energy(pk, name):
     """The 60-site pf + g9/2 space (12p + 12n, J_z = 0 and 2) on a short ramp
