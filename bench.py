@@ -76,7 +76,8 @@ def run_schedule(workload, prec: str, warmup: int, steps: int, D_main: int, seed
     return dict(energy=energy, walls=walls, tot=tot)
 
 
-def plateaus(name: str, prec: str, Ds, per: int, tol: float, trunc_eps: float = 0.0, d_min: int = 0):
+def plateaus(name: str, prec: str, Ds, per: int, tol: float, trunc_eps: float = 0.0, d_min: int = 0,
+             n_states: int = 1):
     """Energy against discarded weight along a D schedule of plateaus (`per`
     sweeps at each D), with the sweep time and the H_eff GEMM throughput of the
     last sweep of each plateau; one JSON line per plateau."""
@@ -86,7 +87,7 @@ def plateaus(name: str, prec: str, Ds, per: int, tol: float, trunc_eps: float = 
     h = WORKLOADS[name].hamiltonian()
     sp = h.space
     ctx = pk.Context(precision=PREC[prec], davidson_tol=tol, noise=1e-4, noise_sweeps=2, seed=1507,
-                     trunc_eps=trunc_eps, d_min=d_min)
+                     trunc_eps=trunc_eps, d_min=d_min, n_states=n_states)
     ctx.load_hamiltonian(sp.species, sp.two_m, h.eps, h.V.ravel(), h.n_p, h.n_n, h.two_M)
     peak = PEAK[prec]
     for D in Ds:
@@ -106,6 +107,7 @@ def plateaus(name: str, prec: str, Ds, per: int, tol: float, trunc_eps: float = 
                 g[kn] = {"tflops": tf, "frac_of_peak": tf / peak}
         print(json.dumps({"workload": name, "precision": prec, "D": D, "energy": r["energy"],
                           "trunc_eps": trunc_eps, "d_min": d_min, "kept_max": r["kept_max"],
+                          "n_states": n_states, "energy_excited": r["energy_excited"] if n_states == 2 else None,
                           "discarded_max": r["discarded_max"], "discarded_sum": r["discarded_sum"],
                           "sweep_s": wall, "heff_tflops": r["heff_flops"] / max(r["heff_seconds"], 1e-12) / 1e12,
                           "products_low": r["products_low"], "products_fp64": r["products_fp64"],
@@ -332,6 +334,7 @@ def main():
     ap.add_argument("--per", type=int, default=2)
     ap.add_argument("--trunc-eps", type=float, default=0.0, help="plateaus: DBSS truncation error (0 = fixed D)")
     ap.add_argument("--d-min", type=int, default=0, help="plateaus: DBSS minimum block states")
+    ap.add_argument("--n-states", type=int, default=1, help="plateaus: 2 = the two lowest states at once")
     ap.add_argument("--batched", type=int, metavar="K",
                     help="independent small solves: K instances one at a time vs dmrg_sweep_many")
     args = ap.parse_args()
@@ -350,7 +353,7 @@ def main():
     if args.plateaus:
         for p in [x.strip() for x in args.precisions.split(",") if x.strip()]:
             plateaus(args.plateaus, p, [int(x) for x in args.D_list.split(",")], args.per, args.tol,
-                     args.trunc_eps, args.d_min)
+                     args.trunc_eps, args.d_min, args.n_states)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs one GPU; the multi-GPU path (term-sharded H_eff with an "
