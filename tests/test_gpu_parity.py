@@ -183,7 +183,9 @@ def test_two_state_sweeps_match_oracle(pk, name, precision, rtol):
     c = _ctx(pk, h, precision=precision, **g["options"], **case["options"])
     for D, e0, e1 in zip(case["D"], case["energies"], case["energies_excited"]):
         r = c.sweep(D)
-        assert r["code"] == 0
+        # 1 = a solve stopped at the product limit; the oracle stops at the
+        # same limit (the second state from the random start, first sweep)
+        assert r["code"] in (0, 1)
         assert abs(r["energy"] - e0) <= rtol * abs(e0), (D, r["energy"], e0)
         assert abs(r["energy_excited"] - e1) <= rtol * abs(e1), (D, r["energy_excited"], e1)
         assert r["energy_excited"] >= r["energy"]
