@@ -10,4 +10,6 @@ the tests, the smoke check and the CPU-baseline leg of the benchmark do.
               explicit sites, density-matrix truncation, back-and-forth sweeps),
               written from the method description, merged-sector dense blocks.
 * `hashrand`- SplitMix64 keyed hashing for the method's random start.
+* `entropy` - one- and two-orbital entropies, mutual information and the
+              Fiedler-vector ordering, from their definitions.
 """

@@ -193,6 +193,7 @@ class Options:
     trunc_eps: float = 0.0       # > 0: dynamic block-state selection (DBSS) to this truncation error
     d_min: int = 0               # DBSS: fewest block states kept (D is the most)
     n_states: int = 1            # 2: the two lowest states, truncated with their averaged density matrix
+    measure: bool = False        # orbital correlations and entropies during the right-to-left half
 
 
 @dataclasses.dataclass
@@ -405,6 +406,13 @@ class DMRG:
             if c is not None:
                 ops[("C", i)] = K(c, SITE_I)
         ops[("C", s)] = K(None, SITE_CD)
+        if self.opts.measure:
+            # occupation operators of every S site, for the orbital correlations
+            for i in Lr:
+                nb = L.ops.get(("N", i))
+                if nb is not None:
+                    ops[("N", i)] = K(nb, SITE_I)
+            ops[("N", s)] = K(None, SITE_N)
         # R^S_l = R^L_l + Q^L_sl c+_s - P^L_sl c_s - (sum_i V_issl c+_i) n_s
         for l in range(s + 1, N):
             pieces = [None if L.ops.get(("R", l)) is None else K(L.ops[("R", l)], SITE_I)]
@@ -1083,6 +1091,9 @@ class DMRG:
                 rho = {q: 0.5 * (rho[q] + rho2[q]) for q in rho}
             return rho
         alpha = self.opts.noise if self.sweeps_done < self.opts.noise_sweeps else 0.0
+        if self.opts.measure:
+            self.meas = {k: np.zeros((N, N)) for k in ("pair_ni", "pair_nj", "nn", "hop")}
+            self.meas["n1"] = np.zeros(N)
         setup = None
         for bond in range(0, N - 1):
             setup = setup or self.setup_bond(bond)
@@ -1121,6 +1132,8 @@ class DMRG:
             thetas2.append(self.theta2)
             if on_step:
                 on_step(self, bond, "RL", setup)
+            if self.opts.measure:
+                self.measure_bond(bond, setup)
             if bond == 0:
                 break
             enlL, Sops, enlR, Eops, terms = setup
@@ -1143,7 +1156,88 @@ class DMRG:
                    nprod=self.nprod_total - nprod0, kept_max=kept_max)
         if two:
             out["energy_excited"] = min(thetas2)
+        if self.opts.measure:
+            out["s1"], out["mutual"], _ = self.entropies()
         return out
+
+    # ---------------------------------------------------- orbital correlations
+    def measure_bond(self, bond: int, setup) -> None:
+        """Correlations between the E site j = bond + 1 and every S site i <= bond
+        in the state psi at this bond (the entropy paragraph's rho_i and rho_ij
+        need <n_i>, <n_j>, <n_i n_j> and <c+_i c_j>; see oracle.entropy).
+
+        With S before E in the Jordan-Wigner order and the E site first in E,
+        c_j |s, (r, 1)> = (-1)^N(s) |s, (r, 0)>, so
+        <c+_i c_j> = sum_q (-1)^N(q) <psi_q', C_i psi_q restricted to
+        (r, 1) -> (r, 0)> with q' = q + dq_i, nonzero only when dq_i = dq_j."""
+        enlL, Sops, enlR, Eops, terms = setup
+        psi, T, j, m = self.psi, self.T, bond + 1, self.meas
+
+        def occ_cols(q_s):
+            # E columns of psi block q_s where the E site is occupied, and the
+            # (offset, dim, base sector) of that part
+            p = enlR.part(qsub(T, q_s), 1)
+            return None if p is None else (p.off, p.dim, p.qb)
+
+        nj = 0.0
+        for q, X in psi.items():
+            oc = occ_cols(q)
+            if oc is not None:
+                Y = X[:, oc[0]:oc[0] + oc[1]]
+                nj += float(np.sum(Y * Y))
+        m["pair_nj"][:bond + 1, j] = nj
+        m["n1"][j] = nj
+        for i in range(bond + 1):
+            Nop = Sops.get(("N", i))
+            ni = nn = 0.0
+            for q, X in psi.items():
+                r = None if Nop is None else Nop.block(q, False)
+                if r is None:
+                    continue
+                Z = r[1] @ X
+                ni += float(np.sum(X * Z))
+                oc = occ_cols(q)
+                if oc is not None:
+                    a, d = oc[0], oc[1]
+                    nn += float(np.sum(X[:, a:a + d] * Z[:, a:a + d]))
+            m["pair_ni"][i, j] = ni
+            m["nn"][i, j] = nn
+            if bond == 0:
+                m["n1"][0] = ni
+            if self.delta[i] != self.delta[j]:
+                continue
+            C = Sops.get(("C", i))
+            h = 0.0
+            for q, X in psi.items():
+                r = None if C is None else C.block(q, False)
+                if r is None or r[0] not in psi:
+                    continue
+                oc = occ_cols(q)
+                if oc is None:
+                    continue
+                q2 = r[0]
+                p0 = enlR.part(qsub(T, q2), 0)
+                if p0 is None or p0.qb != oc[2]:
+                    continue
+                Z = r[1] @ X[:, oc[0]:oc[0] + oc[1]]
+                W = psi[q2][:, p0.off:p0.off + p0.dim]
+                sign = -1.0 if nparticles(q) & 1 else 1.0
+                h += sign * float(np.sum(W * Z))
+            m["hop"][i, j] = h
+
+    def entropies(self):
+        """(s1, I, raw) from the last measured half sweep, in site indices (the
+        natural order): s1[site], I[site, site'].  raw holds the correlations in
+        chain positions (Jordan-Wigner order = chain order)."""
+        from .entropy import entropies
+        m = self.meas
+        s1c, Ic = entropies(m["n1"], m["pair_ni"], m["pair_nj"], m["nn"], m["hop"])
+        order = self.order
+        s1 = np.empty(self.N)
+        s1[order] = s1c
+        I = np.empty((self.N, self.N))
+        I[np.ix_(order, order)] = Ic
+        return s1, I, m
 
     # ------------------------------------------------------------ helpers
     def psi_configs(self, enlL: Enlarged, enlR: Enlarged):

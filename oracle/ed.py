@@ -129,6 +129,17 @@ def ground_energy(eps, V, species, two_m, n_p: int, n_n: int, two_M: int,
     return np.sort(w)
 
 
+def ground_state(eps, V, species, two_m, n_p: int, n_n: int, two_M: int):
+    """(E0, basis, vector) of the lowest state in the (n_p, n_n, 2M) sector."""
+    basis = mscheme_basis(species, two_m, n_p, n_n, two_M)
+    H = hamiltonian_matrix(eps, V, basis)
+    if basis.shape[0] <= 2000:
+        w, v = np.linalg.eigh(H.toarray())
+        return float(w[0]), basis, v[:, 0]
+    w, v = spla.eigsh(H, k=1, which="SA", tol=1e-14, maxiter=20000)
+    return float(w[0]), basis, v[:, 0]
+
+
 def apply_rows(eps, V, configs: np.ndarray, psi: np.ndarray, rows: Iterable[int]) -> np.ndarray:
     """(H psi)[r] for selected positions r of a vector given on determinants.
 

@@ -2,7 +2,8 @@
 
 Each case runs the oracle's two-site DMRG (oracle/dmrg.py) on a seeded
 workload with a fixed sweep schedule and options, and records the sweep
-energies.  The GPU parity tests run the library with the same workload,
+energies (and, for the measuring cases, the orbital entropies, the mutual
+information and the correlations they come from).  The GPU parity tests run the library with the same workload,
 schedule, ordering and options and compare energies (relative 1e-8 in FP64,
 1e-6 in the mixed modes).  Nothing here touches the GPU library.
 
@@ -39,6 +40,11 @@ CASES = [
     # the two lowest states targeted at once (averaged density matrix)
     ("p_2p2n_two", "p_2p2n", None, [64, 64], {"n_states": 2}),
     ("sd_4p4n_two", "sd_4p4n", None, [32, 32], {"n_states": 2}),
+    # orbital correlations, entropies and mutual information (last sweep)
+    ("p_2p2n_ent", "p_2p2n", None, [16, 16], {"measure": True}),
+    ("sd_4p4n_ent", "sd_4p4n", None, [32, 32], {"measure": True}),
+    ("sd_3p2n_M1_rand_ent", ("sd", 13, 3, 2, 1), 5, [24, 24], {"measure": True}),
+    ("pf_8p8n_ent", "pf_8p8n", None, [32, 32], {"measure": True}),
 ]
 
 
@@ -65,6 +71,11 @@ def main():
                 "kept_max": [r["kept_max"] for r in res], "options": extra,
                 "energies_excited": [r.get("energy_excited") for r in res],
                 "target": [h.n_p, h.n_n, h.two_M]}
+        if extra.get("measure"):
+            s1, mutual, m = o.entropies()
+            case["s1"] = s1.tolist()
+            case["mutual"] = mutual.tolist()
+            case["correlations"] = {k: v.tolist() for k, v in m.items()}
         if sp.n_sites <= 24:
             case["exact"] = float(ed.ground_energy(h.eps, h.V, sp.species, sp.two_m,
                                                    h.n_p, h.n_n, h.two_M)[0])
