@@ -98,7 +98,9 @@ def plateaus(name: str, prec: str, Ds, per: int, tol: float, trunc_eps: float = 
             torch.cuda.synchronize()
             wall = time.perf_counter() - t
             log(f"[{name} {prec}] D={D} sweep {k}: E={r['energy']:.9f} discarded max {r['discarded_max']:.2e} "
-                f"kept max {r['kept_max']} {wall:.1f}s products lo/64={r['products_low']}/{r['products_fp64']}")
+                f"kept max {r['kept_max']} {wall:.1f}s products lo/64={r['products_low']}/{r['products_fp64']} "
+                f"not converged {r['not_converged']}"
+                + (f" E1={r['energy_excited']:.9f}" if n_states == 2 else ""))
         free, total = torch.cuda.mem_get_info()
         g = {}
         for ph, kn in (("gemm1", "k_heff_z"), ("gemm2", "k_heff_y")):
@@ -114,6 +116,70 @@ def plateaus(name: str, prec: str, Ds, per: int, tol: float, trunc_eps: float = 
                           "not_converged": r["not_converged"], "gemm_phases": g,
                           "device_mem_used_gb": (total - free) / 1e9}), flush=True)
     ctx.close()
+
+
+def preprocess(name: str, prec: str, D_pre: int, sweeps_pre: int, Ds, per: int, tol: float):
+    """The preprocessing phase of the entropy paragraph and what it buys:
+    measuring sweeps at a small D give the one-orbital entropies and the
+    mutual information; the Fiedler-vector ordering of the latter is then run
+    against the natural order on the same D schedule (fresh contexts, the same
+    options).  One JSON line for the measurement, one per plateau and order."""
+    import numpy as np
+    import torch
+    import paper_1507_00161_amd as pk
+    from workloads import WORKLOADS
+    h = WORKLOADS[name].hamiltonian()
+    sp = h.space
+    n = sp.n_sites
+    common = dict(precision=PREC[prec], davidson_tol=tol, noise=1e-4, noise_sweeps=2, seed=1507)
+    ctx = pk.Context(measure=1, **common)
+    ctx.load_hamiltonian(sp.species, sp.two_m, h.eps, h.V.ravel(), h.n_p, h.n_n, h.two_M)
+    for k in range(sweeps_pre):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        r = ctx.sweep(D_pre)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t
+        log(f"[{name} {prec}] measuring sweep {k} D={D_pre}: E={r['energy']:.9f} {wall:.1f}s "
+            f"(measurement {r['measure_seconds']:.2f}s)")
+    m = ctx.orbital_entropies()
+    ctx.close()
+    order, fval = pk.fiedler_ordering(m["mutual"])
+    I = m["mutual"]
+
+    def dist(o):
+        pos = np.empty(n, np.int64)
+        pos[np.asarray(o)] = np.arange(n)
+        return float(np.sum(np.triu(I * (pos[:, None] - pos[None, :]) ** 2.0, 1)))
+
+    iu = np.triu_indices(n, 1)
+    top = np.argsort(I[iu])[::-1][:8]
+    print(json.dumps({"workload": name, "precision": prec, "phase": "measure", "D": D_pre,
+                      "sweeps": sweeps_pre, "energy": r["energy"], "sweep_s": wall,
+                      "measure_s": r["measure_seconds"],
+                      "s1": {"min": float(m["s1"].min()), "max": float(m["s1"].max()),
+                             "mean": float(m["s1"].mean())},
+                      "mutual_max": float(I.max()),
+                      "top_pairs": [[int(iu[0][x]), int(iu[1][x]), float(I[iu][x])] for x in top],
+                      "fiedler_value": fval, "ordering": order.tolist(),
+                      "I_dist_natural": dist(np.arange(n)), "I_dist_fiedler": dist(order)}), flush=True)
+    for label, ordering in (("natural", None), ("fiedler", order)):
+        c = pk.Context(**common)
+        c.load_hamiltonian(sp.species, sp.two_m, h.eps, h.V.ravel(), h.n_p, h.n_n, h.two_M)
+        for D in Ds:
+            for k in range(per):
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                r = c.sweep(D, ordering)
+                torch.cuda.synchronize()
+                wall = time.perf_counter() - t
+                log(f"[{name} {prec} {label}] D={D} sweep {k}: E={r['energy']:.9f} "
+                    f"discarded max {r['discarded_max']:.2e} {wall:.1f}s")
+            print(json.dumps({"workload": name, "precision": prec, "phase": "production", "order": label,
+                              "D": D, "energy": r["energy"], "discarded_max": r["discarded_max"],
+                              "discarded_sum": r["discarded_sum"], "sweep_s": wall,
+                              "not_converged": r["not_converged"]}), flush=True)
+        c.close()
 
 
 def cpu_baseline(budget_s: float = 20.0):
@@ -335,6 +401,10 @@ def main():
     ap.add_argument("--trunc-eps", type=float, default=0.0, help="plateaus: DBSS truncation error (0 = fixed D)")
     ap.add_argument("--d-min", type=int, default=0, help="plateaus: DBSS minimum block states")
     ap.add_argument("--n-states", type=int, default=1, help="plateaus: 2 = the two lowest states at once")
+    ap.add_argument("--preprocess", metavar="WORKLOAD",
+                    help="measuring sweeps at --D-pre, Fiedler ordering, then --D-list plateaus in both orders")
+    ap.add_argument("--D-pre", type=int, default=256)
+    ap.add_argument("--sweeps-pre", type=int, default=2)
     ap.add_argument("--batched", type=int, metavar="K",
                     help="independent small solves: K instances one at a time vs dmrg_sweep_many")
     args = ap.parse_args()
@@ -349,6 +419,11 @@ def main():
         return
     if args.batched:
         batched(args.batched)
+        return
+    if args.preprocess:
+        for p in args.precisions.split(","):
+            preprocess(args.preprocess, p, args.D_pre, args.sweeps_pre, [int(x) for x in args.D_list.split(",")],
+                       args.per, args.tol)
         return
     if args.plateaus:
         for p in [x.strip() for x in args.precisions.split(",") if x.strip()]:

@@ -75,6 +75,13 @@ typedef struct dmrg_options {
      * weights.  dmrg_energy, dmrg_heff_layout/apply and dmrg_get_psi refer to
      * the first state; the second state's energy is in the sweep statistics. */
     int32_t n_states;
+    /* 1: measure the orbital correlations of the (first) state during the
+     * right-to-left half of every sweep, for the one-orbital entropies and the
+     * two-orbital mutual information of the paper's entropy paragraph
+     * (dmrg_orbital_entropies).  At bond b the state gives <n_j>, and for every
+     * i <= b <n_i>, <n_i n_j> and <c+_i c_j>, with j = b + 1.  Left blocks then
+     * carry the occupation operator of each of their sites.  0 (default): off. */
+    int32_t measure;
 } dmrg_options;
 
 typedef struct dmrg_sweep_stats {
@@ -113,6 +120,7 @@ typedef struct dmrg_sweep_stats {
     double reduce_seconds;             /* split-K reductions of those launches */
     int64_t kept_max;                  /* most block states kept by a truncation of the sweep */
     double energy_excited;             /* n_states = 2: lowest step energy of the second state (MeV) */
+    double measure_seconds;            /* measure = 1: host wall time of the correlation measurements */
 } dmrg_sweep_stats;
 
 typedef struct dmrg_ctx dmrg_ctx;
@@ -190,6 +198,41 @@ dmrg_status dmrg_heff_configs(dmrg_ctx* ctx, uint64_t* configs);
  * A NULL or repeated context -> DMRG_ERR_ARG before any work. */
 dmrg_status dmrg_sweep_many(dmrg_ctx** ctxs, int32_t n, const int32_t* const* orderings,
                             const int32_t* D, dmrg_sweep_stats* out);
+
+/* One- and two-orbital entropies of the last sweep run with measure = 1
+ * (the entropy paragraph).  An orbital is a site (one m-state).  With the
+ * proton and neutron numbers and 2M fixed, rho_i = diag(1 - <n_i>, <n_i>)
+ * and rho_ij, in the basis |00>, |01>, |10>, |11> of (n_i, n_j), holds
+ * <(1-n_i)(1-n_j)>, <(1-n_i) n_j>, <n_i (1-n_j)>, <n_i n_j> on the diagonal
+ * and <c+_i c_j> between |01> and |10>.  s = -Tr rho ln rho, and the mutual
+ * information is I_ij = s_i + s_j - s_ij (>= 0; the paper prints the
+ * opposite sign), all of a pair's values taken from the state at bond j - 1
+ * of the chain.  Host outputs, in site indices (the order of
+ * dmrg_load_hamiltonian, whatever the chain ordering):
+ *   s1[n_sites]                  one-orbital entropies (may be NULL)
+ *   mutual[n_sites * n_sites]    I, row-major, symmetric, zero diagonal (may be NULL)
+ *   n1[n_sites]                  <n_i> (may be NULL)
+ *   nn[n_sites * n_sites]        <n_i n_j>, symmetric, <n_i> on the diagonal (may be NULL)
+ *   hop[n_sites * n_sites]       <c+_i c_j> with the Jordan-Wigner order of the
+ *                                chain, symmetric, zero diagonal (may be NULL)
+ * DMRG_ERR_STATE if no sweep with measure = 1 has completed since the
+ * Hamiltonian or the ordering last changed. */
+dmrg_status dmrg_orbital_entropies(dmrg_ctx* ctx, double* s1, double* mutual, double* n1, double* nn,
+                                   double* hop);
+
+/* Entropy-based ordering (the entropy paragraph, eta = 2): the chain order
+ * that sorts the sites by the Fiedler vector, the eigenvector of the second
+ * smallest eigenvalue of the Laplacian L = diag(sum_j I_ij) - I of the n x n
+ * row-major mutual-information matrix `mutual` (host).  That vector minimises
+ * sum_ij I_ij (x_i - x_j)^2 over real x of unit norm orthogonal to the
+ * constants, the relaxation of sum_ij I_ij |p_i - p_j|^2 over chain
+ * positions p.  Its sign is fixed so that the first nonzero component (in
+ * site order) is negative; equal components keep site order.  Writes the
+ * permutation ordering[n] (chain position -> site), usable as the ordering
+ * of dmrg_sweep; *fiedler_value (may be NULL) receives the eigenvalue.  Host
+ * only (cyclic Jacobi); needs no context or device.  Errors: DMRG_ERR_ARG
+ * for n < 1, NULL pointers, or a matrix that is not finite and symmetric. */
+dmrg_status dmrg_fiedler_ordering(const double* mutual, int32_t n, int32_t* ordering, double* fiedler_value);
 
 const char* dmrg_status_string(dmrg_status s);
 const char* dmrg_last_error(const dmrg_ctx* ctx);

@@ -31,7 +31,8 @@ class Options(ctypes.Structure):
                 ("tie_tol", ctypes.c_double), ("device", ctypes.c_int32),
                 ("stream", ctypes.c_void_p), ("mem_cap_bytes", ctypes.c_uint64),
                 ("scratch_bytes", ctypes.c_uint64), ("trunc_eps", ctypes.c_double),
-                ("d_min", ctypes.c_int32), ("n_states", ctypes.c_int32)]
+                ("d_min", ctypes.c_int32), ("n_states", ctypes.c_int32),
+                ("measure", ctypes.c_int32)]
 
 
 class SweepStats(ctypes.Structure):
@@ -50,7 +51,7 @@ class SweepStats(ctypes.Structure):
                 ("gemm1_flops", ctypes.c_double), ("gemm2_flops", ctypes.c_double),
                 ("gemm1_bytes", ctypes.c_double), ("gemm2_bytes", ctypes.c_double),
                 ("reduce_seconds", ctypes.c_double), ("kept_max", ctypes.c_int64),
-                ("energy_excited", ctypes.c_double)]
+                ("energy_excited", ctypes.c_double), ("measure_seconds", ctypes.c_double)]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -78,6 +79,8 @@ def declare(lib: ctypes.CDLL) -> ctypes.CDLL:
         "dmrg_get_psi": (I32, [P, P]),
         "dmrg_heff_configs": (I32, [P, P]),
         "dmrg_sweep_many": (I32, [P, I32, P, P, P]),
+        "dmrg_orbital_entropies": (I32, [P, P, P, P, P, P]),
+        "dmrg_fiedler_ordering": (I32, [P, I32, P, ctypes.POINTER(D)]),
         "dmrg_status_string": (ctypes.c_char_p, [I32]),
         "dmrg_last_error": (ctypes.c_char_p, [P]),
     }
@@ -219,6 +222,32 @@ class Context:
         out = np.empty(dim, np.uint64)
         self._check(self._lib.dmrg_heff_configs(self._h, _ptr(out)))
         return out
+
+
+    def orbital_entropies(self) -> dict:
+        """Entropies and correlations of the last sweep run with measure=1
+        (dmrg_orbital_entropies): s1[site], mutual[site, site'], n1, nn, hop."""
+        n = self.n_sites
+        out = {"s1": np.empty(n), "mutual": np.empty((n, n)), "n1": np.empty(n),
+               "nn": np.empty((n, n)), "hop": np.empty((n, n))}
+        self._check(self._lib.dmrg_orbital_entropies(self._h, *[_ptr(out[k]) for k in
+                                                                ("s1", "mutual", "n1", "nn", "hop")]))
+        return out
+
+
+def fiedler_ordering(mutual, lib: Optional[ctypes.CDLL] = None):
+    """(ordering, Fiedler value) of a mutual-information matrix (dmrg_fiedler_ordering)."""
+    lib = lib if lib is not None else library()
+    m = _f64(mutual)
+    n = m.shape[0]
+    if m.ndim != 2 or m.shape[1] != n:
+        raise ValueError("mutual must be a square matrix")
+    order = np.empty(n, np.int32)
+    val = ctypes.c_double()
+    st = lib.dmrg_fiedler_ordering(_ptr(m), n, _ptr(order), ctypes.byref(val))
+    if st != 0:
+        raise DMRGError(st, "dmrg_fiedler_ordering: n < 1 or a matrix that is not finite and symmetric")
+    return order, val.value
 
 
 def sweep_many(contexts, D, orderings=None):

@@ -62,6 +62,7 @@ void dmrg_default_options(dmrg_options* o) {
     o->trunc_eps = 0.0;
     o->d_min = 0;
     o->n_states = 1;
+    o->measure = 0;
 }
 
 dmrg_status dmrg_create(const dmrg_options* opt, dmrg_ctx** out) {
@@ -72,7 +73,8 @@ dmrg_status dmrg_create(const dmrg_options* opt, dmrg_ctx** out) {
     if (opt) o = *opt;
     if (o.precision < 0 || o.precision > 2 || o.davidson_tol <= 0 || o.davidson_max_iter < 1 ||
         o.davidson_max_subspace < 2 || o.davidson_max_subspace > 32 || o.noise < 0 || o.tie_tol < 0 ||
-        !(o.trunc_eps >= 0) || o.d_min < 0 || o.n_states < 1 || o.n_states > 2) {
+        !(o.trunc_eps >= 0) || o.d_min < 0 || o.n_states < 1 || o.n_states > 2 ||
+        (o.measure != 0 && o.measure != 1)) {
         g_create_err = "invalid option value";
         return DMRG_ERR_ARG;
     }
@@ -131,6 +133,19 @@ dmrg_status dmrg_energy(dmrg_ctx* c, double* E) {
 
 dmrg_status dmrg_get_psi(dmrg_ctx* c, double* psi) {
     return guarded(c, [&] { return c->eng->get_psi(psi); });
+}
+
+dmrg_status dmrg_orbital_entropies(dmrg_ctx* c, double* s1, double* mutual, double* n1, double* nn, double* hop) {
+    return guarded(c, [&] { return c->eng->orbital_entropies(s1, mutual, n1, nn, hop); });
+}
+
+dmrg_status dmrg_fiedler_ordering(const double* mutual, int32_t n, int32_t* ordering, double* fiedler_value) {
+    if (!mutual || !ordering || n < 1) return DMRG_ERR_ARG;
+    try {
+        return dm::fiedler_ordering(mutual, n, ordering, fiedler_value) ? DMRG_OK : DMRG_ERR_ARG;
+    } catch (...) {
+        return DMRG_ERR_ARG;
+    }
 }
 
 dmrg_status dmrg_heff_configs(dmrg_ctx* c, uint64_t* configs) {

@@ -121,6 +121,19 @@ struct DiagTask {
 };
 int diag(Ctx* c, double* const* bufs, const DiagTask* d_tasks, int ntasks, const DiagTerm* d_terms);
 
+// -------------------------------------------------- segment dot products
+// partial[t] = coef_t * sum_{r < rows, c < cols} A[a_off + r*lda + c] * B[b_off + r*ldb + c]
+// with A = bufs[a_buf], B = bufs[b_buf]; then out[o] = sum of partial[t] over
+// t in [obeg[o], obeg[o+1]) in that order.  FP64, deterministic.
+struct SegDot {
+    double coef;
+    int64_t a_off, b_off;
+    int32_t rows, cols, lda, ldb;
+    uint8_t a_buf, b_buf, pad0, pad1;
+};
+int seg_dots(Ctx* c, double* const* bufs, const SegDot* d_segs, int nseg, const int32_t* d_obeg, int nout,
+             double* d_partial, double* d_out);
+
 // ----------------------------------------------------- FP64 vector kernels
 // V holds nvec vectors of length n at stride ldv.
 // d_out[v * ostride] = V_v . w

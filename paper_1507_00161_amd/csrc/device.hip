@@ -754,6 +754,51 @@ int diag(Ctx* c, double* const* bufs, const DiagTask* tasks, int ntasks, const D
     return 0;
 }
 
+// ================================================== segment dot products
+// One work-group per segment: waves stride over rows, lanes over columns.
+__global__ void __launch_bounds__(256) k_seg_dots(DBufs bufs, const SegDot* __restrict__ segs,
+                                                  double* __restrict__ partial) {
+    const SegDot s = segs[blockIdx.x];
+    const double* A = bufs.p[s.a_buf] + s.a_off;
+    const double* B = bufs.p[s.b_buf] + s.b_off;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    double acc = 0.0;
+    for (int r = wave; r < s.rows; r += 4) {
+        const double* a = A + (int64_t)r * s.lda;
+        const double* b = B + (int64_t)r * s.ldb;
+        for (int c = lane; c < s.cols; c += 64) acc += a[c] * b[c];
+    }
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    __shared__ double sh[4];
+    if (lane == 0) sh[wave] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) partial[blockIdx.x] = s.coef * (((sh[0] + sh[1]) + sh[2]) + sh[3]);
+}
+
+__global__ void __launch_bounds__(256) k_seg_sum(const double* __restrict__ partial,
+                                                 const int32_t* __restrict__ obeg, int nout,
+                                                 double* __restrict__ out) {
+    const int o = blockIdx.x * blockDim.x + threadIdx.x;
+    if (o >= nout) return;
+    double s = 0.0;
+    for (int t = obeg[o]; t < obeg[o + 1]; ++t) s += partial[t];
+    out[o] = s;
+}
+
+int seg_dots(Ctx* c, double* const* bufs, const SegDot* segs, int nseg, const int32_t* obeg, int nout,
+             double* partial, double* out) {
+    if (nout <= 0) return 0;
+    DBufs b;
+    for (int i = 0; i < kMaxBufs; ++i) b.p[i] = i < 3 ? bufs[i] : nullptr;
+    if (nseg > 0) {
+        hipLaunchKernelGGL(k_seg_dots, dim3(nseg), dim3(256), 0, c->stream, b, segs, partial);
+        LAUNCHCHK(c);
+    }
+    hipLaunchKernelGGL(k_seg_sum, dim3((nout + 255) / 256), dim3(256), 0, c->stream, partial, obeg, nout, out);
+    LAUNCHCHK(c);
+    return 0;
+}
+
 // ============================================================ FP64 vectors
 constexpr int kDotBlocks = 512;
 

@@ -592,6 +592,7 @@ dmrg_status Engine::load(int n, const int32_t* species, const int32_t* two_m, co
     psi1_.reset();
     init_ = false;
     loaded_ = false;
+    meas_valid_ = false;
     have_energy_ = false;
     sweeps_done_ = 0;
     for (int i = 0; i < n; ++i) {
@@ -660,6 +661,7 @@ dmrg_status Engine::set_order(const int32_t* ordering) {
     }
     if (init_ && ord == order_) return DMRG_OK;
     order_ = ord;
+    meas_valid_ = false;
     eps_.assign(N_, 0.0);
     V_.assign((size_t)N_ * N_ * N_ * N_, 0.0);
     delta_.assign(N_, QN());
@@ -831,6 +833,17 @@ static std::vector<std::pair<Key, Formula>> left_formulas(const Engine& e, const
         Formula f;
         push_ident(f, S_CD, 1.0);
         out.push_back({{'C', s, 0}, f});
+    }
+    if (e.measuring()) {
+        // occupation operators of every S site, for the orbital correlations
+        for (int i = L.lo; i < L.hi; ++i) {
+            Formula f;
+            push(f, S_I, F.one({'N', i, 0}));
+            if (!f.empty()) out.push_back({{'N', i, 0}, f});
+        }
+        Formula f;
+        push_ident(f, S_N, 1.0);
+        out.push_back({{'N', s, 0}, f});
     }
     // R^S_l = R^L_l + Q^L_sl c+_s - P^L_sl c_s - (sum_i V_issl c+_i) n_s
     for (int l = s + 1; l < N; ++l) {
@@ -2578,6 +2591,7 @@ dmrg_status Engine::steps(const int32_t* ordering, int D, int64_t max_steps, boo
         acc_ = dmrg_sweep_stats{};
         sweep_min_ = INFINITY;
         sweep_min1_ = INFINITY;
+        reset_measure();
     }
     TRY(ensure_dv(cur_->dim, std::max(2, std::min(32, opt_.davidson_max_subspace))));
     dmrg_status ret = DMRG_OK;
@@ -2621,6 +2635,11 @@ dmrg_status Engine::steps(const int32_t* ordering, int D, int64_t max_steps, boo
         ++done;
         ++sweep_steps_;
         acc_.steps += 1;
+        if (opt_.measure && dir_ == 1) {
+            const double tm = now();
+            TRY(measure_bond(*cur_));
+            acc_.measure_seconds += now() - tm;
+        }
         bool last = dir_ == 0 ? bond_ == N_ - 2 : bond_ == 0;
         if (last) {
             if (dir_ == 0) {
@@ -2629,6 +2648,7 @@ dmrg_status Engine::steps(const int32_t* ordering, int D, int64_t max_steps, boo
                 dir_ = 0;
                 sweeps_done_ += 1;
                 have_energy_ = true;
+                if (opt_.measure) meas_valid_ = true;
                 energy_ = sweep_min_;
                 acc_.energy = sweep_min_;
                 acc_.energy_excited = opt_.n_states == 2 ? sweep_min1_ : 0.0;
@@ -2640,6 +2660,7 @@ dmrg_status Engine::steps(const int32_t* ordering, int D, int64_t max_steps, boo
                 acc_ = dmrg_sweep_stats{};
                 sweep_min_ = INFINITY;
                 sweep_min1_ = INFINITY;
+                reset_measure();
                 t0 = now();
             }
             continue;
@@ -2661,6 +2682,236 @@ dmrg_status Engine::steps(const int32_t* ordering, int D, int64_t max_steps, boo
     acc_.sweep_seconds += now() - t0;
     if (st) *st = acc_;
     return ret;
+}
+
+// ================================================== orbital correlations
+void Engine::reset_measure() {
+    if (!opt_.measure) return;
+    const size_t n2 = (size_t)N_ * N_;
+    m_n1_.assign(N_, 0.0);
+    m_pni_.assign(n2, 0.0);
+    m_pnj_.assign(n2, 0.0);
+    m_nn_.assign(n2, 0.0);
+    m_hop_.assign(n2, 0.0);
+    meas_valid_ = false;
+}
+
+// At bond b of the right-to-left half, with E site j = b + 1: <n_j>, and for
+// every S site i <= b <n_i>, <n_i n_j> and <c+_i c_j> in the state psi (the
+// inputs of rho_i and rho_ij, the entropy paragraph).  Phase 1 (grouped GEMM,
+// FP64): Z = N_i psi_x per psi block, and, for i of j's species and 2m,
+// T = C_i psi_x on the E columns where j is occupied.  Phase 2 (segment dot
+// products): <n_i> = <psi, Z>, <n_i n_j> = <psi, Z> over the columns with j
+// occupied, <n_j> likewise with psi itself, and <c+_i c_j> = sum_x
+// (-1)^N(S sector of x) <psi_x2 on the columns (r, 0), T on (r, 1)>: with S
+// before E in the Jordan-Wigner order and j first in E,
+// c_j |s, (r, 1)> = (-1)^N(s) |s, (r, 0)>.  The i are taken in batches whose
+// intermediates fit in a few copies of psi.
+dmrg_status Engine::measure_bond(Bond& B) {
+    const Enl &S = B.S, &E = B.E;
+    const int b = B.b, j = b + 1;
+    const int nb = (int)B.pm_S.size();
+    const int64_t psi_elems = B.dim;
+    auto esub = [&](int x, int sigma) -> const Sub* {
+        if (x < 0) return nullptr;
+        const int i = E.msub[B.pm_E[x]][sigma];
+        return i < 0 ? nullptr : &E.sub[i];
+    };
+    // outputs: 0 = <n_j>; 1 + 3 i + {0, 1, 2} = <n_i>, <n_i n_j>, <c+_i c_j>
+    const int nout = 1 + 3 * (b + 1);
+    std::vector<std::vector<dmrgdev::SegDot>> segs_of(nout);
+    auto seg = [&](int out, double coef, int abuf, int64_t aoff, int lda, int bbuf, int64_t boff, int ldb,
+                   int rows, int cols) {
+        if (rows <= 0 || cols <= 0) return;
+        const int step = std::max(1, 32768 / cols);
+        for (int r0 = 0; r0 < rows; r0 += step) {
+            dmrgdev::SegDot sd{};
+            sd.coef = coef;
+            sd.a_off = aoff + (int64_t)r0 * lda;
+            sd.b_off = boff + (int64_t)r0 * ldb;
+            sd.rows = std::min(step, rows - r0);
+            sd.cols = cols;
+            sd.lda = lda;
+            sd.ldb = ldb;
+            sd.a_buf = (uint8_t)abuf;
+            sd.b_buf = (uint8_t)bbuf;
+            segs_of[out].push_back(sd);
+        }
+    };
+    for (int x = 0; x < nb; ++x) {
+        const Sub* e1 = esub(x, 1);
+        if (!e1) continue;
+        const int ds = S.md[B.pm_S[x]], de = E.md[B.pm_E[x]];
+        seg(0, 1.0, 0, B.poff[x] + e1->off, de, 0, B.poff[x] + e1->off, de, ds, e1->dim);
+    }
+    const OpSet& ops = B.Sops;
+    const int64_t cap = std::max<int64_t>(8 * psi_elems, (int64_t)1 << 24);
+    Buf outb;
+    TRY(alloc_buf(outb, (size_t)nout * sizeof(double)));
+    for (int i0 = 0; i0 <= b;) {
+        GB g;
+        int64_t phi = 0;
+        int i1 = i0;
+        // each i needs at most two psi-sized intermediates (Z, and T)
+        while (i1 <= b && (i1 == i0 || phi + 2 * psi_elems + 64 * nb <= cap)) {
+            const int i = i1++;
+            const int on = 1 + 3 * i;
+            if (const Op* Nop = ops.get({'N', i, 0})) {
+                for (int x = 0; x < nb; ++x) {
+                    const int mS = B.pm_S[x];
+                    const int ds = S.md[mS], de = E.md[B.pm_E[x]];
+                    const Sub* e1 = esub(x, 1);
+                    const int64_t zo = phi;
+                    bool any = false;
+                    for (int o : S.msub[mS]) {
+                        if (o < 0) continue;
+                        g.begin();
+                        bool got = false;
+                        for (int i2 : S.msub[mS]) {
+                            if (i2 < 0) continue;
+                            for (int q : Nop->acting(i2, false)) {
+                                const Blk& bk = Nop->blk[q];
+                                if (bk.out != o) continue;
+                                g.chunk(1.0, 1, bk.off, bk.cols, false, 0, B.poff[x] + (int64_t)S.sub[i2].off * de, de,
+                                        false, S.sub[i2].dim);
+                                got = true;
+                            }
+                        }
+                        if (!got) continue;
+                        const int64_t po = B.poff[x] + (int64_t)S.sub[o].off * de;
+                        const int64_t zz = zo + (int64_t)S.sub[o].off * de;
+                        g.end(2, zz, de, S.sub[o].dim, de, 0);
+                        any = true;
+                        seg(on, 1.0, 0, po, de, 2, zz, de, S.sub[o].dim, de);
+                        if (e1) seg(on + 1, 1.0, 0, po + e1->off, de, 2, zz + e1->off, de, S.sub[o].dim, e1->dim);
+                    }
+                    if (any) phi += ((int64_t)ds * de + 31) / 32 * 32;
+                }
+            }
+            const Op* C = delta_[i] == delta_[j] ? ops.get({'C', i, 0}) : nullptr;
+            if (!C) continue;
+            for (int x = 0; x < nb; ++x) {
+                const Sub* e1 = esub(x, 1);
+                if (!e1) continue;
+                const int mS = B.pm_S[x];
+                const int de = E.md[B.pm_E[x]];
+                int m_out = -1;
+                for (int i2 : S.msub[mS]) {
+                    if (i2 < 0) continue;
+                    for (int q : C->acting(i2, false)) m_out = S.sub[C->blk[q].out].m;
+                }
+                if (m_out < 0) continue;
+                const int x2 = B.blk_of_S[m_out];
+                const Sub* e0 = esub(x2, 0);
+                if (!e0 || e0->base != e1->base) continue;
+                const int de2 = E.md[B.pm_E[x2]];
+                const int w = e1->dim;
+                const double sign = (S.mq[mS].n() & 1) ? -1.0 : 1.0;
+                const int64_t to = phi;
+                bool any = false;
+                for (int o : S.msub[m_out]) {
+                    if (o < 0) continue;
+                    g.begin();
+                    bool got = false;
+                    for (int i2 : S.msub[mS]) {
+                        if (i2 < 0) continue;
+                        for (int q : C->acting(i2, false)) {
+                            const Blk& bk = C->blk[q];
+                            if (bk.out != o) continue;
+                            g.chunk(1.0, 1, bk.off, bk.cols, false, 0,
+                                    B.poff[x] + (int64_t)S.sub[i2].off * de + e1->off, de, false, S.sub[i2].dim);
+                            got = true;
+                        }
+                    }
+                    if (!got) continue;
+                    const int64_t tt = to + (int64_t)S.sub[o].off * w;
+                    g.end(2, tt, w, S.sub[o].dim, w, 0);
+                    any = true;
+                    seg(on + 2, sign, 0, B.poff[x2] + (int64_t)S.sub[o].off * de2 + e0->off, de2, 2, tt, w,
+                        S.sub[o].dim, w);
+                }
+                if (any) phi += ((int64_t)S.md[m_out] * w + 31) / 32 * 32;
+            }
+        }
+        // bounds of every operand and output against its buffer (psi, ops, phi)
+        const int64_t lim[3] = {psi_elems, ops.size, phi};
+        auto inside = [&](int buf, int64_t off, int64_t rows, int64_t cols, int64_t ld) {
+            return buf >= 0 && buf < 3 && off >= 0 && rows >= 1 && cols >= 1 && cols <= ld &&
+                   off + (rows - 1) * ld + cols <= lim[buf];
+        };
+        for (const auto& ob : g.obs) {
+            if (!inside(2, ob.coff, ob.M, ob.Nn, ob.ldc)) return fail(DMRG_ERR_DEVICE, "internal: measurement output out of range");
+            for (int64_t c = ob.cb; c < ob.ce; ++c) {
+                const GemmChunk& ch = g.chunks[c];
+                if (!inside(ch.a_buf, ch.a_off, ob.M, ch.K, ch.lda) || !inside(ch.b_buf, ch.b_off, ch.K, ob.Nn, ch.ldb))
+                    return fail(DMRG_ERR_DEVICE, "internal: measurement operand out of range");
+            }
+        }
+        const int o0 = i0 == 0 ? 0 : 1 + 3 * i0, o1 = 1 + 3 * i1;
+        std::vector<dmrgdev::SegDot> flat;
+        std::vector<int32_t> obeg;
+        for (int o = o0; o < o1; ++o) {
+            obeg.push_back((int32_t)flat.size());
+            for (const auto& sd : segs_of[o]) {
+                if (!inside(sd.a_buf, sd.a_off, sd.rows, sd.cols, sd.lda) ||
+                    !inside(sd.b_buf, sd.b_off, sd.rows, sd.cols, sd.ldb))
+                    return fail(DMRG_ERR_DEVICE, "internal: measurement dot out of range");
+                flat.push_back(sd);
+            }
+        }
+        obeg.push_back((int32_t)flat.size());
+        Buf phib, sb, obb, pb;
+        TRY(alloc_buf(phib, std::max<int64_t>(phi, 1) * sizeof(double)));
+        GemmPlan p;
+        TRY(finish_plan(*this, g, p));
+        BufTable bufs{psi_.p, ops.pool.p, phib.p};
+        TRY(run_gemm(dmrgdev::P_F64, bufs, p));
+        if (!flat.empty()) TRY(upload(sb, flat));
+        TRY(upload(obb, obeg));
+        TRY(alloc_buf(pb, std::max<size_t>(flat.size(), 1) * sizeof(double)));
+        double* dbufs[3] = {psi_.d(), ops.pool.d(), phib.d()};
+        DEV(dmrgdev::seg_dots(dev_, dbufs, flat.empty() ? nullptr : sb.as<dmrgdev::SegDot>(), (int)flat.size(),
+                              obb.as<int32_t>(), o1 - o0, pb.d(), outb.d() + o0));
+        DEV(dmrgdev::sync(dev_));
+        i0 = i1;
+    }
+    std::vector<double> h(nout);
+    DEV(dmrgdev::d2h(dev_, h.data(), outb.d(), (size_t)nout * sizeof(double)));
+    const double nj = h[0];
+    m_n1_[j] = nj;
+    for (int i = 0; i <= b; ++i) {
+        const size_t at = (size_t)i * N_ + j;
+        m_pni_[at] = h[1 + 3 * i];
+        m_pnj_[at] = nj;
+        m_nn_[at] = h[2 + 3 * i];
+        m_hop_[at] = h[3 + 3 * i];
+    }
+    if (b == 0) m_n1_[0] = h[1];
+    return DMRG_OK;
+}
+
+dmrg_status Engine::orbital_entropies(double* s1, double* mutual, double* n1, double* nn, double* hop) {
+    if (!meas_valid_) return fail(DMRG_ERR_STATE, "no completed sweep with measure = 1");
+    const int n = N_;
+    for (int p = 0; p < n; ++p) {
+        const int a = order_[p];
+        if (s1) s1[a] = entropy_one(m_n1_[p]);
+        if (n1) n1[a] = m_n1_[p];
+        if (mutual) mutual[(size_t)a * n + a] = 0.0;
+        if (nn) nn[(size_t)a * n + a] = m_n1_[p];
+        if (hop) hop[(size_t)a * n + a] = 0.0;
+        for (int q = p + 1; q < n; ++q) {
+            const int c = order_[q];
+            const size_t at = (size_t)p * n + q;
+            const double ni = m_pni_[at], nj = m_pnj_[at];
+            if (mutual)
+                mutual[(size_t)a * n + c] = mutual[(size_t)c * n + a] =
+                    entropy_one(ni) + entropy_one(nj) - entropy_two(ni, nj, m_nn_[at], m_hop_[at]);
+            if (nn) nn[(size_t)a * n + c] = nn[(size_t)c * n + a] = m_nn_[at];
+            if (hop) hop[(size_t)a * n + c] = hop[(size_t)c * n + a] = m_hop_[at];
+        }
+    }
+    return DMRG_OK;
 }
 
 // ========================================================== queries

@@ -261,6 +261,8 @@ public:
     dmrg_status energy(double* E);
     dmrg_status get_psi(double* host);
     dmrg_status configs(uint64_t* out);
+    dmrg_status orbital_entropies(double* s1, double* mutual, double* n1, double* nn, double* hop);
+    bool measuring() const { return opt_.measure != 0; }
 
     const std::string& error() const { return err_; }
     dmrg_status fail(dmrg_status s, const std::string& msg) {
@@ -370,10 +372,23 @@ private:
     dmrg_status ensure_partials(int64_t slots);
     Buf partial_;
     dmrg_status ensure_dv(int64_t n, int kmax);
+    // orbital correlations of the current sweep's right-to-left half, in chain
+    // positions: n1[p]; for p < q (at p * N + q) the pair's <n_p>, <n_q>,
+    // <n_p n_q> and <c+_p c_q>, all from the state at bond q - 1
+    dmrg_status measure_bond(Bond& B);
+    void reset_measure();
+    std::vector<double> m_n1_, m_pni_, m_pnj_, m_nn_, m_hop_;
+    bool meas_valid_ = false;
     std::vector<std::vector<double>> selection_iso(const std::vector<int>& dims, int D, int tag,
                                                    int pos, const std::vector<QN>& qs, bool mix,
                                                    std::vector<int>& kept,
                                                    std::vector<std::vector<int>>* chosen);
 };
+
+// entropy.cpp: entropies of rho_i and rho_ij from the correlations, and the
+// Fiedler-vector ordering of a mutual-information matrix (false: bad input)
+double entropy_one(double n_i);
+double entropy_two(double n_i, double n_j, double nn_ij, double hop_ij);
+bool fiedler_ordering(const double* mutual, int n, int32_t* ordering, double* fiedler_value);
 
 }  // namespace dm

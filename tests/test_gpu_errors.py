@@ -92,6 +92,39 @@ def test_invalid_truncation_options_rejected(pk):
         assert e.value.status == -1
 
 
+def test_orbital_entropies_need_a_measuring_sweep(pk):
+    """dmrg_orbital_entropies: DMRG_ERR_STATE without measure = 1, before the
+    first measuring sweep has completed, and after the ordering changed until
+    the next sweep completes."""
+    h = _h()
+    c = pk.Context()
+    _load(c, h)
+    c.sweep(16)
+    with pytest.raises(pk.DMRGError) as e:
+        c.orbital_entropies()
+    assert e.value.status == -4
+    c = pk.Context(measure=1)
+    _load(c, h)
+    with pytest.raises(pk.DMRGError) as e:
+        c.orbital_entropies()
+    assert e.value.status == -4
+    c.sweep_steps(16, 3)              # a partial sweep measures nothing complete
+    with pytest.raises(pk.DMRGError) as e:
+        c.orbital_entropies()
+    assert e.value.status == -4
+    c.sweep(16)
+    m = c.orbital_entropies()
+    assert np.all(np.isfinite(m["s1"])) and np.all(m["s1"] >= 0)
+    order = np.arange(12)[::-1].copy()
+    c.sweep_steps(16, 1, ordering=order)
+    with pytest.raises(pk.DMRGError) as e:
+        c.orbital_entropies()
+    assert e.value.status == -4
+    with pytest.raises(pk.DMRGError) as e:
+        pk.Context(measure=2)
+    assert e.value.status == -1
+
+
 def test_not_converged_warning_keeps_valid_results(pk):
     h = _h()
     c = pk.Context(davidson_max_iter=1)

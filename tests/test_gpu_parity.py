@@ -8,7 +8,10 @@
 * sweep energies equal the oracle's (tests/golden, written by the oracle
   alone) to 1e-8 relative in FP64 and 1e-6 in the mixed modes;
 * exact diagonalisation and closed forms: p shell at exact D, the degenerate
-  pairing model at the pf 8p+8n size.
+  pairing model at the pf 8p+8n size;
+* orbital correlations, entropies and mutual information of measuring sweeps
+  equal the oracle's, the exact ground vector's at full rank, and the
+  pairing closed form at the pf 8p+8n size.
 """
 import json
 import os
@@ -232,6 +235,104 @@ def test_pairing_closed_form_pf_8p8n(pk):
     for _ in range(2):
         r = c.sweep(1024)
     assert abs(r["energy"] - (16 * eps0 - 56 * G)) < 1e-8
+
+
+# ------------------------------------ orbital correlations and entropies
+def _chain_view(m, order, n):
+    """Library outputs (site indices) viewed in chain positions, as the oracle
+    stores its raw correlations."""
+    o = np.arange(n) if order is None else np.asarray(order)
+    return m["n1"][o], m["nn"][np.ix_(o, o)], m["hop"][np.ix_(o, o)]
+
+
+# Entropy tolerance: the golden states are converged to a Davidson residual of
+# 1e-9, so with gaps above 0.01 MeV the correlations (quadratic in psi) agree
+# to ~1e-7, and entropies (slope |ln(n/(1-n))| < 10 for these occupations) to
+# ~1e-6.
+@pytest.mark.parametrize("name", ["p_2p2n_ent", "sd_4p4n_ent", "sd_3p2n_M1_rand_ent", "pf_8p8n_ent"])
+@pytest.mark.parametrize("precision,rtol", [(0, 1e-8), (1, 1e-6)])
+def test_entropies_match_oracle(pk, name, precision, rtol):
+    """Measuring sweeps: energies, the correlations <n_i>, <n_i n_j>, <c+_i c_j>
+    and the one-orbital entropies and mutual information equal the oracle's."""
+    g = _golden()
+    case = g["cases"][name]
+    h = _golden_ham(case["workload"])
+    n = h.space.n_sites
+    order = None if case["ordering_seed"] is None else random_ordering(n, case["ordering_seed"])
+    c = _ctx(pk, h, precision=precision, measure=1, **g["options"])
+    for D, e_ref in zip(case["D"], case["energies"]):
+        r = c.sweep(D, order)
+        assert r["code"] == 0
+        assert abs(r["energy"] - e_ref) <= rtol * abs(e_ref), (D, r["energy"], e_ref)
+    m = c.orbital_entropies()
+    assert np.abs(m["s1"] - np.array(case["s1"])).max() < 1e-6
+    assert np.abs(m["mutual"] - np.array(case["mutual"])).max() < 1e-6
+    assert np.array_equal(m["mutual"], m["mutual"].T) and np.all(np.diag(m["mutual"]) == 0.0)
+    n1, nn, hop = _chain_view(m, order, n)
+    cor = case["correlations"]
+    iu = np.triu_indices(n, 1)
+    assert np.abs(n1 - np.array(cor["n1"])).max() < 1e-7
+    assert np.abs(nn[iu] - np.array(cor["nn"])[iu]).max() < 1e-7
+    assert np.abs(hop[iu] - np.array(cor["hop"])[iu]).max() < 1e-7
+
+
+def test_entropies_at_full_rank_equal_ed(pk):
+    """p shell at a bond dimension above the exact Schmidt rank: entropies and
+    mutual information equal those of the exact ground vector, brute force
+    over determinants, in any chain ordering."""
+    from oracle import entropy
+    h = WORKLOADS["p_2p2n"].hamiltonian()
+    sp = h.space
+    E0, basis, vec = ed.ground_state(h.eps, h.V, sp.species, sp.two_m, 2, 2, 0)
+    s1e, Ie = entropy.entropies_of_vector(basis, vec, sp.n_sites)
+    n, nn, hop = entropy.correlations_from_vector(basis, vec, sp.n_sites)
+    for order in (None, random_ordering(12, 4)):
+        c = _ctx(pk, h, davidson_tol=1e-10, noise=1e-4, noise_sweeps=1, measure=1)
+        for _ in range(2):
+            r = c.sweep(64, order)
+        assert abs(r["energy"] - E0) < 1e-10
+        m = c.orbital_entropies()
+        assert np.abs(m["s1"] - s1e).max() < 1e-8 and np.abs(m["mutual"] - Ie).max() < 1e-8
+        assert np.abs(m["n1"] - n).max() < 1e-9
+        iu = np.triu_indices(sp.n_sites, 1)
+        assert np.abs(m["nn"][iu] - nn[iu]).max() < 1e-9
+        if order is None:   # <c+_i c_j> carries the Jordan-Wigner order of the chain
+            assert np.abs(m["hop"][iu] - hop[iu]).max() < 1e-9
+
+
+def test_entropies_pairing_closed_form_pf_8p8n(pk):
+    """Degenerate pairing in the 56Ni-sized space (pf, 40 sites, 8p + 8n):
+    the ground state is the product of the seniority-zero states of 4 pairs in
+    Omega = 10 for each species, so <n_i> = 2/5; time-reversed partners have
+    rho = diag(3/5, 0, 0, 2/5); other like-particle pairs have
+    <n_i n_j> = 4*3/(10*9) = 2/15 and no hopping; protons and neutrons are
+    uncorrelated.  Every entropy and mutual information at full size."""
+    import math
+    sp = make_space("pf")
+    h = make_pairing(sp, 0.35, -1.25, 8, 8)
+    c = _ctx(pk, h, davidson_tol=1e-9, noise=1e-4, noise_sweeps=2, seed=5, measure=1)
+    for _ in range(2):
+        r = c.sweep(1024)
+    assert abs(r["energy"] - (16 * -1.25 - 56 * 0.35)) < 1e-8
+    m = c.orbital_entropies()
+
+    def ent(ws):
+        return -sum(w * math.log(w) for w in ws if w > 0)
+
+    h1 = ent([0.4, 0.6])
+    other = 2 * h1 - ent([1 / 3, 4 / 15, 4 / 15, 2 / 15])
+    assert np.abs(m["n1"] - 0.4).max() < 1e-7
+    assert np.abs(m["s1"] - h1).max() < 1e-6
+    n = sp.n_sites
+    want = np.zeros((n, n))
+    for i in range(n):
+        for j in range(n):
+            if i == j or sp.species[i] != sp.species[j]:
+                continue
+            partner = sp.shell[i] == sp.shell[j] and sp.two_m[i] == -sp.two_m[j]
+            want[i, j] = h1 if partner else other
+    assert np.abs(m["mutual"] - want).max() < 1e-6
+    assert np.abs(m["hop"]).max() < 1e-7
 
 
 def test_sweep_many_matches_single_contexts(pk):
