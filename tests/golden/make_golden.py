@@ -45,6 +45,8 @@ CASES = [
     ("sd_4p4n_ent", "sd_4p4n", None, [32, 32], {"measure": True}),
     ("sd_3p2n_M1_rand_ent", ("sd", 13, 3, 2, 1), 5, [24, 24], {"measure": True}),
     ("pf_8p8n_ent", "pf_8p8n", None, [32, 32], {"measure": True}),
+    ("sd_4p4n_two_ent", "sd_4p4n", None, [32, 32], {"measure": True, "n_states": 2}),
+    ("sd_4p4n_dbss_ent", "sd_4p4n", None, [128, 128], {"measure": True, "trunc_eps": 1e-3, "d_min": 8}),
 ]
 
 
