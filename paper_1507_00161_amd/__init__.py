@@ -100,6 +100,14 @@ def library() -> ctypes.CDLL:
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: run `python build.py` (hipcc, gfx950) first")
+        # PyTorch ships its own HIP and HSA runtimes under other file names.  When
+        # this library (and with it the system runtime) is loaded first and torch
+        # afterwards, the library's device query finds no device; with torch
+        # loaded first both runtimes work.  So load torch first when it exists.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         _lib = declare(ctypes.CDLL(LIB_PATH))
     return _lib
 

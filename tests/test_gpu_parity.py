@@ -340,6 +340,38 @@ def test_entropies_pairing_closed_form_pf_8p8n(pk):
     assert np.abs(m["hop"]).max() < 1e-7
 
 
+def test_entropies_full_size_pf_8p8n_D2048(pk):
+    """The benchmark's workload and schedule (pf 8p+8n, D = 512, 512, 1024,
+    1024, 2048) with measuring sweeps: mixed FP32 and FP64 give the same
+    energy (1e-6) and the same entropies and mutual information (1e-5); at
+    this size 0 <= s_i <= ln 2, 0 <= I_ij <= 2 ln 2 (subadditivity, which a
+    pair's rho_ij from one normalised state obeys), occupations in [0, 1]
+    summing to about 8 per species (each from its own bond), and
+    |<c+_i c_j>| <= 1/2."""
+    import math
+    h = WORKLOADS["pf_8p8n"].hamiltonian()
+    out = {}
+    for prec in (1, 0):
+        c = _ctx(pk, h, precision=prec, davidson_tol=1e-7, noise=1e-4, noise_sweeps=2, seed=1507, measure=1)
+        for D in (512, 512, 1024, 1024, 2048):
+            r = c.sweep(D)
+            assert r["code"] in (0, 1)
+        out[prec] = (r["energy"], c.orbital_entropies())
+        c.close()
+    (e32, m32), (e64, m64) = out[1], out[0]
+    assert abs(e32 - e64) <= 1e-6 * abs(e64)
+    assert np.abs(m32["s1"] - m64["s1"]).max() < 1e-5
+    assert np.abs(m32["mutual"] - m64["mutual"]).max() < 1e-5
+    for m in (m32, m64):
+        s1, I, n1, nn, hop = m["s1"], m["mutual"], m["n1"], m["nn"], m["hop"]
+        assert s1.min() >= 0.0 and s1.max() <= math.log(2) + 1e-12
+        assert I.min() >= -1e-9 and I.max() <= 2 * math.log(2) + 1e-12
+        assert np.array_equal(I, I.T)
+        assert n1.min() >= -1e-12 and n1.max() <= 1.0 + 1e-12
+        assert abs(n1[:20].sum() - 8.0) < 0.05 and abs(n1[20:].sum() - 8.0) < 0.05
+        assert (np.abs(hop) <= 0.5 + 1e-12).all()   # |<c+_i c_j>| <= sqrt(<n_i><1 - n_j>)-type bound
+
+
 def test_sweep_many_matches_single_contexts(pk):
     """Concurrent sweeps of independent contexts (several host threads, one
     stream each) give the results of one-at-a-time sweeps."""
