@@ -209,11 +209,23 @@ def cpu_baseline(budget_s: float = 20.0):
     except _Stop:
         pass
     threads = max([i.get("num_threads", 1) for i in threadpool_info() if i.get("user_api") == "blas"] or [1])
-    return {"value": o.heff_flops / max(o.heff_seconds, 1e-12) / 1e12, "unit": "TFLOP/s",
-            "cores": int(threads), "kind": "oracle",
+    value = o.heff_flops / max(o.heff_seconds, 1e-12) / 1e12
+    # one-thread figure: H_eff products at the bond where the sample stopped, BLAS on one thread
+    from threadpoolctl import threadpool_limits
+    terms = o.setup_bond(o.psi_bond)[4]
+    f0, s0, n1 = o.heff_flops, o.heff_seconds, 0
+    t1 = time.perf_counter()
+    with threadpool_limits(limits=1, user_api="blas"):
+        while time.perf_counter() - t1 < budget_s / 4:
+            o.heff_apply(terms, o.psi)
+            n1 += 1
+    one = (o.heff_flops - f0) / max(o.heff_seconds - s0, 1e-12) / 1e12
+    return {"value": value, "unit": "TFLOP/s", "cores": int(threads), "kind": "oracle",
+            "single_thread_value": one,
             "sample": f"NumPy oracle, pf 8p+8n, first sweep at D=64 stopped after {budget_s:.0f} s "
                       f"({steps[0]} two-site steps, {o.nprod_total} H_eff products); its own "
-                      f"merged-sector matmul flops / time in H_eff products"}
+                      f"merged-sector matmul flops / time in H_eff products; single_thread_value: "
+                      f"{n1} products at bond {o.psi_bond} with BLAS on one thread"}
 
 
 # the kernels and the engine that builds their task lists: counters taken for
