@@ -111,6 +111,27 @@ def test_heff_full_size_pf_8p8n_D2048_sampled_rows(pk, torch_dev):
     assert np.linalg.norm(y16 - y64) < 2e-2 * np.linalg.norm(y64)
 
 
+@pytest.mark.parametrize("name,D", [("pfg9_12p12n", 2048), ("pfg9_12p12n_M2", 1024)])
+def test_heff_full_size_pfg9_sampled_rows(pk, torch_dev, name, D):
+    """The 64Ge-sized pf + g9/2 space (60 sites, 12p + 12n, 2M = 0 and 4) at
+    the middle bond: sampled output rows of H_eff psi against Slater-Condon
+    rows, FP64 to 1e-11, and the mixed products within their precision."""
+    h = WORKLOADS[name].hamiltonian()
+    c = _ctx(pk, h, davidson_tol=1e-6, select_basis=1, seed=5)
+    c.sweep_steps(D, 29)
+    bond, dim, qn, dims = c.heff_layout()
+    assert bond == 29 and dim > 10000
+    cfg = c.heff_configs()
+    rng = np.random.default_rng(2)
+    x = rng.normal(size=dim)
+    rows = rng.choice(dim, 80, replace=False)
+    ref = ed.apply_rows(h.eps, h.V, cfg, x, rows)
+    y64 = _apply(c, x, torch_dev, 0)
+    assert np.abs(y64[rows] - ref).max() < 1e-11 * max(1.0, np.abs(ref).max())
+    y32 = _apply(c, x, torch_dev, 1)
+    assert np.linalg.norm(y32 - y64) < 1e-5 * np.linalg.norm(y64)
+
+
 def test_heff_is_symmetric_and_linear(pk, torch_dev):
     h = WORKLOADS["sd_4p4n"].hamiltonian()
     c = _ctx(pk, h, davidson_tol=1e-8, noise=1e-4, noise_sweeps=1, seed=2)
