@@ -443,7 +443,7 @@ def main():
                      args.trunc_eps, args.d_min, args.n_states)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs one GPU; the multi-GPU path (term-sharded H_eff with an "
+        print("bench.py: the library runs on one GPU; the multi-GPU path (term-sharded H_eff with an "
               "all-reduce of H_eff.psi) is designed but not built, so --gpus must be 1", file=sys.stderr)
         sys.exit(2)
     import torch
