@@ -107,7 +107,7 @@ def test_fiedler_ordering_matches_the_oracle(lib):
     from oracle import entropy
     rng = np.random.default_rng(11)
     mats = []
-    for n in (2, 3, 5, 12, 40, 60):
+    for n in (2, 3, 5, 12, 40, 60, 120):
         a = rng.uniform(0.0, 1.0, (n, n)) ** 3
         a = np.triu(a, 1)
         mats.append(a + a.T)

@@ -412,3 +412,24 @@ def test_sweep_many_matches_single_contexts(pk):
         assert o["status"] == 0 and abs(o["energy"] - e) <= 1e-12 * abs(e)
     for c in ctxs:
         c.close()
+
+
+def test_sweep_many_measuring_contexts_match_single(pk):
+    """Measuring sweeps of independent contexts advanced together (one host
+    thread and stream each) give the entropies of one-at-a-time sweeps."""
+    from workloads import batched_instances
+    hs = [WORKLOADS["p_2p2n"].hamiltonian()] + [w.hamiltonian() for w in batched_instances(4)]
+    single = []
+    for h in hs:
+        c = _ctx(pk, h, davidson_tol=1e-9, seed=3, measure=1)
+        c.sweep(24)
+        single.append(c.orbital_entropies())
+        c.close()
+    ctxs = [_ctx(pk, h, davidson_tol=1e-9, seed=3, measure=1) for h in hs]
+    st, out = pk.sweep_many(ctxs, [24] * len(hs))
+    assert st in (0, 1)
+    for c, ref in zip(ctxs, single):
+        m = c.orbital_entropies()
+        assert np.abs(m["s1"] - ref["s1"]).max() <= 1e-12
+        assert np.abs(m["mutual"] - ref["mutual"]).max() <= 1e-12
+        c.close()
