@@ -180,6 +180,29 @@ def dbss_count(w_desc, D: int, eps: float, d_min: int) -> int:
     return min(max(n, d_min), D, len(w_desc))
 
 
+def truncation_count(w_desc, D: int, tie_tol: float, trunc_eps: float = 0.0, d_min: int = 0) -> int:
+    """Number of density-matrix weights kept (w_desc: all weights, descending).
+
+    The two-site paragraph truncates the block basis to the M (here D) states
+    of largest weight; with DBSS the count comes from the truncation error
+    (dbss_count).  Reading for ties: when the weights on both sides of the cut
+    differ by at most tie_tol, the cut would split states the density matrix
+    cannot tell apart, so the count is lowered to the end of the previous tie
+    group (D_eff <= D); if no such end exists the count is raised to the end of
+    the group that straddles the cut.  Zero weights form one such group."""
+    n = min(D, len(w_desc))
+    if trunc_eps > 0.0:
+        n = dbss_count(w_desc, D, trunc_eps, d_min)
+    n0 = n
+    while 0 < n < len(w_desc) and w_desc[n - 1] - w_desc[n] <= tie_tol:
+        n -= 1
+    if n == 0:
+        n = n0
+        while n < len(w_desc) and w_desc[n - 1] - w_desc[n] <= tie_tol:
+            n += 1
+    return n
+
+
 @dataclasses.dataclass
 class Options:
     davidson_tol: float = 1e-7
@@ -800,16 +823,7 @@ class DMRG:
             for x in range(len(w)):
                 allw.append((float(w[x]), q, x))
         allw.sort(key=lambda t: -t[0])
-        n = min(D, len(allw))
-        if o.trunc_eps > 0.0:
-            n = self.dbss_count([t[0] for t in allw], D)
-        n0 = n
-        while 0 < n < len(allw) and allw[n - 1][0] - allw[n][0] <= o.tie_tol:
-            n -= 1
-        if n == 0:
-            n = n0
-            while n < len(allw) and allw[n - 1][0] - allw[n][0] <= o.tie_tol:
-                n += 1
+        n = truncation_count([t[0] for t in allw], D, o.tie_tol, o.trunc_eps, o.d_min)
         kept = allw[:n]
         disc = 1.0 - sum(t[0] for t in kept)
         iso = {}
