@@ -37,7 +37,12 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def run_schedule(workload, prec: str, warmup: int, steps: int, D_main: int, seed: int, tol: float):
+def run_schedule(workload, prec: str, warmup: int, steps: int, D_main: int, seed: int, tol: float,
+                 check: bool = False):
+    """The benchmark schedule in one precision: `warmup` sweeps of the ramp
+    (then D_main), `steps` timed sweeps at D_main; with `check`, one more
+    (untimed) sweep in which every mixed solve is repeated in FP64 from the
+    same guess on the same H_eff (dmrg_check_fp64)."""
     import torch
     import paper_1507_00161_amd as pk
     h = workload.hamiltonian()
@@ -45,10 +50,12 @@ def run_schedule(workload, prec: str, warmup: int, steps: int, D_main: int, seed
     ctx = pk.Context(precision=PREC[prec], davidson_tol=tol, noise=1e-4, noise_sweeps=2, seed=seed)
     ctx.load_hamiltonian(sp.species, sp.two_m, h.eps, h.V.ravel(), h.n_p, h.n_n, h.two_M)
     ramp = list(workload.D_schedule)
+    energies = []      # every sweep of the schedule, warm-up included
     for w in range(warmup):
         D = ramp[w] if w < len(ramp) else D_main
         t = time.perf_counter()
         r = ctx.sweep(D)
+        energies.append(r["energy"])
         log(f"[{prec}] warmup sweep {w} D={D}: E={r['energy']:.9f} {time.perf_counter() - t:.1f}s "
             f"products lo/64={r['products_low']}/{r['products_fp64']} not converged {r['not_converged']}")
     torch.cuda.synchronize()
@@ -62,6 +69,7 @@ def run_schedule(workload, prec: str, warmup: int, steps: int, D_main: int, seed
         torch.cuda.synchronize()
         walls.append(time.perf_counter() - t)
         energy = r["energy"]
+        energies.append(energy)
         for key, v in r.items():
             if isinstance(v, (int, float)) and key not in ("energy", "last_theta", "code", "status"):
                 tot[key] = tot.get(key, 0) + v
@@ -72,8 +80,17 @@ def run_schedule(workload, prec: str, warmup: int, steps: int, D_main: int, seed
             f"{r['renorm_seconds']:.2f}s (density {r['density_seconds']:.2f}, eig {r['eig_seconds']:.2f}, "
             f"renormalize {r['renormalize_seconds']:.2f}, predict {r['predict_seconds']:.2f}), "
             f"blocking+plans {r['blocking_seconds']:.2f}s")
+    chk = None
+    if check and prec != "fp64":
+        ctx.check_fp64(True)
+        t = time.perf_counter()
+        r = ctx.sweep(D_main)
+        chk = {"solves": int(r["check_solves"]), "max_rel": r["check_max_rel"], "energy": r["energy"]}
+        log(f"[{prec}] check sweep D={D_main}: every solve repeated in FP64 from the same guess, "
+            f"{chk['solves']} pairs, max |theta - theta_fp64| / |theta_fp64| = {chk['max_rel']:.3e} "
+            f"({time.perf_counter() - t:.1f}s)")
     ctx.close()
-    return dict(energy=energy, walls=walls, tot=tot)
+    return dict(energy=energy, walls=walls, tot=tot, energies=energies, check=chk)
 
 
 def plateaus(name: str, prec: str, Ds, per: int, tol: float, trunc_eps: float = 0.0, d_min: int = 0,
@@ -182,10 +199,17 @@ def preprocess(name: str, prec: str, D_pre: int, sweeps_pre: int, Ds, per: int, 
         c.close()
 
 
-def cpu_baseline(budget_s: float = 20.0):
-    """The oracle's own H_eff.psi throughput on a bounded sample of the same
-    workload: its first sweep at D = 64, stopped after `budget_s` seconds."""
+def cpu_baseline(budget_s: float = 25.0, D: int = 256):
+    """The oracle's H_eff.psi throughput beside the GPU's on one bounded
+    sample of the benchmark workload: the first sweep at D (same options as
+    the benchmark) is run step by step by the NumPy oracle until `budget_s`
+    seconds have passed, then the same steps by the library in FP64 and mixed
+    FP32.  Both rates are algorithmic flops (the library's count for the
+    products of each step, cheaper contraction order) per second of product
+    time, so they are in one unit; the oracle's products per step are its own."""
+    import torch
     from threadpoolctl import threadpool_info
+    import paper_1507_00161_amd as pk
     from oracle import dmrg
     from workloads import WORKLOADS
 
@@ -194,38 +218,54 @@ def cpu_baseline(budget_s: float = 20.0):
 
     h = WORKLOADS["pf_8p8n"].hamiltonian()
     sp = h.space
-    o = dmrg.DMRG(h.eps, h.V, sp.species, sp.two_m, h.n_p, h.n_n, h.two_M,
-                  opts=dmrg.Options(davidson_tol=1e-7, noise=1e-4, noise_sweeps=2, seed=1507))
+    opts = dict(davidson_tol=1e-7, noise=1e-4, noise_sweeps=2, seed=1507)
+    o = dmrg.DMRG(h.eps, h.V, sp.species, sp.two_m, h.n_p, h.n_n, h.two_M, opts=dmrg.Options(**opts))
+    steps = []     # per step: oracle products, oracle seconds in products
+    last = [0.0, 0]
     t0 = time.perf_counter()
-    steps = [0]
 
     def hook(oo, bond, direction, setup):
-        steps[0] += 1
+        steps.append((oo.nprod_total - last[1], oo.heff_seconds - last[0]))
+        last[0], last[1] = oo.heff_seconds, oo.nprod_total
         if time.perf_counter() - t0 > budget_s:
             raise _Stop
 
     try:
-        o.sweep(64, on_step=hook)
+        o.sweep(D, on_step=hook)
     except _Stop:
         pass
     threads = max([i.get("num_threads", 1) for i in threadpool_info() if i.get("user_api") == "blas"] or [1])
-    value = o.heff_flops / max(o.heff_seconds, 1e-12) / 1e12
-    # one-thread figure: H_eff products at the bond where the sample stopped, BLAS on one thread
-    from threadpoolctl import threadpool_limits
-    terms = o.setup_bond(o.psi_bond)[4]
-    f0, s0, n1 = o.heff_flops, o.heff_seconds, 0
-    t1 = time.perf_counter()
-    with threadpool_limits(limits=1, user_api="blas"):
-        while time.perf_counter() - t1 < budget_s / 4:
-            o.heff_apply(terms, o.psi)
-            n1 += 1
-    one = (o.heff_flops - f0) / max(o.heff_seconds - s0, 1e-12) / 1e12
-    return {"value": value, "unit": "TFLOP/s", "cores": int(threads), "kind": "oracle",
-            "single_thread_value": one,
-            "sample": f"NumPy oracle, pf 8p+8n, first sweep at D=64 stopped after {budget_s:.0f} s "
-                      f"({steps[0]} two-site steps, {o.nprod_total} H_eff products); its own "
-                      f"merged-sector matmul flops / time in H_eff products; single_thread_value: "
-                      f"{n1} products at bond {o.psi_bond} with BLAS on one thread"}
+    k = len(steps)
+    gpu = {}
+    alg_per_product = None
+    for prec in ("fp64", "fp32"):
+        c = pk.Context(precision=PREC[prec], **opts)
+        c.load_hamiltonian(sp.species, sp.two_m, h.eps, h.V.ravel(), h.n_p, h.n_n, h.two_M)
+        prev = {"heff_flops": 0.0, "heff_seconds": 0.0, "products_low": 0, "products_fp64": 0}
+        rows = []
+        for _ in range(k):
+            r = c.sweep_steps(D, 1)
+            d = {key: r[key] - prev[key] for key in prev}
+            prev = {key: r[key] for key in prev}
+            rows.append(d)
+        torch.cuda.synchronize()
+        c.close()
+        fl = sum(d["heff_flops"] for d in rows)
+        sec = sum(d["heff_seconds"] for d in rows)
+        gpu[prec] = {"tflops": fl / max(sec, 1e-12) / 1e12,
+                     "products": int(sum(d["products_low"] + d["products_fp64"] for d in rows)),
+                     "product_seconds": sec}
+        if prec == "fp64":
+            alg_per_product = [d["heff_flops"] / max(d["products_low"] + d["products_fp64"], 1) for d in rows]
+    cpu_flops = sum(a * n for a, (n, _) in zip(alg_per_product, steps))
+    cpu_sec = sum(t for _, t in steps)
+    return {"value": cpu_flops / max(cpu_sec, 1e-12) / 1e12, "unit": "TFLOP/s", "cores": int(threads),
+            "host_cpus": os.cpu_count(), "kind": "oracle",
+            "products": int(sum(n for n, _ in steps)), "product_seconds": cpu_sec,
+            "gpu_same_sample": gpu,
+            "sample": f"pf 8p+8n, first sweep at D={D} from the hash start, its first {k} two-site steps "
+                      f"(the oracle's {budget_s:.0f} s budget), run by the NumPy oracle (BLAS threads = cores) "
+                      f"and by the library (gpu_same_sample); algorithmic H_eff flops per second of product time"}
 
 
 # the kernels and the engine that builds their task lists: counters taken for
@@ -391,6 +431,35 @@ def batched(k: int, precision: str = "fp32"):
     print(json.dumps(res))
 
 
+ORACLE_SCHEDULE = os.path.join(ROOT, "tests", "golden", "oracle_bench_schedule.json")
+
+
+def vs_oracle(res, wl, args):
+    """Sweep energies of the GPU runs against the oracle's on the same
+    schedule and options (tests/golden/oracle_bench_schedule.json, written by
+    the oracle alone), for the sweeps the oracle has."""
+    try:
+        g = json.load(open(ORACLE_SCHEDULE))
+    except OSError:
+        return None
+    ramp = list(wl.D_schedule)
+    sched = [ramp[w] if w < len(ramp) else args.D for w in range(args.warmup)] + [args.D] * args.steps
+    o = g["options"]
+    if (o["davidson_tol"] != args.tol or o["seed"] != 1507 or o["noise"] != 1e-4 or o["noise_sweeps"] != 2
+            or g["workload"] != "pf_8p8n"):
+        return None
+    n = 0
+    while n < min(len(sched), len(g["D"])) and sched[n] == g["D"][n]:
+        n += 1
+    if n == 0:
+        return None
+    out = {"sweeps": n, "D": sched[:n], "oracle_energies": g["energies"][:n]}
+    for p, r in res.items():
+        rel = [abs(a - b) / abs(b) for a, b in zip(r["energies"][:n], g["energies"][:n])]
+        out[p] = {"rel": rel, "rel_max": max(rel)}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -400,6 +469,7 @@ def main():
     ap.add_argument("--D", type=int, default=2048)
     ap.add_argument("--tol", type=float, default=1e-7)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-check", action="store_true", help="skip the FP64 re-solve sweep of the mixed run")
     ap.add_argument("--summarize-trace", metavar="DIR", help="summarise a rocprofv3 kernel-trace run")
     ap.add_argument("--summarize-counters", nargs=4, metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE"),
                     help="HBM traffic from rocprofv3 --pmc runs of this benchmark and of --copy-reference")
@@ -455,7 +525,8 @@ def main():
     precs = [p.strip() for p in args.precisions.split(",") if p.strip()]
     res = {}
     for p in precs:
-        res[p] = run_schedule(wl, p, args.warmup, args.steps, args.D, seed=1507, tol=args.tol)
+        res[p] = run_schedule(wl, p, args.warmup, args.steps, args.D, seed=1507, tol=args.tol,
+                              check=not args.no_check)
     main_p = "fp32" if "fp32" in res else precs[-1]
     R = res[main_p]
     t = R["tot"]
@@ -466,6 +537,7 @@ def main():
     kdt = t[f"{k}_seconds"] / nl
     kfl = t[f"{k}_flops"] / nl
     achieved = kfl / max(kdt, 1e-12) / 1e12
+    kiss = t[f"{k}_issued_flops"] / nl
     ctype = {"fp64": "double, double, 16", "fp32": "float, float, 32"}.get(main_p, "")
     kname = f"{'k_heff_y' if k == 'gemm2' else 'k_heff_z'}<{ctype}>" if ctype else "k_gemm_bf16"
     traffic = measured_traffic(kname)
@@ -493,11 +565,18 @@ def main():
                      "frac": achieved / PEAK[main_p], "traffic": traffic,
                      "launch_ms": 1e3 * kdt, "launches": int(t[f"{k}_launches"]),
                      "algorithmic_gflop_per_launch": kfl / 1e9,
+                     "issued_gflop_per_launch": kiss / 1e9,
                      "algorithmic_gb_per_launch": t[f"{k}_bytes"] / nl / 1e9,
                      "split_k_reduce_ms_per_launch": 1e3 * t.get("reduce_seconds", 0.0) / nl,
                      "other_phase": {"kernel": oname, "launch_ms": 1e3 * t[f"{ko}_seconds"] / nlo,
                                      "algorithmic_gflop_per_launch": t[f"{ko}_flops"] / nlo / 1e9,
+                                     "issued_gflop_per_launch": t[f"{ko}_issued_flops"] / nlo / 1e9,
                                      "algorithmic_gb_per_launch": t[f"{ko}_bytes"] / nlo / 1e9}},
+        "flop_counts": {"value_counts": "algorithmic: per term and psi block the cheaper of the two "
+                                        "contraction orders, nonzero sub-blocks, intermediates formed once",
+                        "algorithmic_gflop": t["heff_flops"] / 1e9,
+                        "executed_gflop": t["heff_flops_executed"] / 1e9,
+                        "executed_tflops": t["heff_flops_executed"] / max(t["heff_seconds"], 1e-12) / 1e12},
     }
     for p, r in res.items():
         tt = r["tot"]
@@ -507,9 +586,25 @@ def main():
                            "heff_seconds": tt["heff_seconds"]}
     if "fp64" in res and main_p != "fp64":
         e64, em = res["fp64"]["energy"], R["energy"]
-        out["delta_E_rel"] = abs(em - e64) / abs(e64)
-        out["delta_E_MeV"] = em - e64
+        # sweep by sweep along the two trajectories (same schedule, same start)
+        rel = [abs(a - b) / abs(b) for a, b in zip(R["energies"], res["fp64"]["energies"])]
+        nt = args.steps
+        par = {"trajectory_rel_last": abs(em - e64) / abs(e64),
+               "trajectory_rel_max_timed": max(rel[-nt:]),
+               "trajectory_rel_max_all": max(rel),
+               "trajectory_MeV_last": em - e64,
+               "note": "trajectory_*: the mixed and the FP64 GPU runs of the same schedule, sweep by sweep "
+                       "(both truncated and unconverged, so they keep slightly different states)"}
+        if R["check"]:
+            par["fixed_heff_rel_max"] = R["check"]["max_rel"]
+            par["fixed_heff_solves"] = R["check"]["solves"]
+            par["fixed_heff_note"] = ("one extra sweep after the timed ones: at every bond the mixed solve "
+                                      "and an FP64 solve from the same guess on the same H_eff")
+        out["parity"] = par
         out["sweep_speedup_vs_fp64"] = out["fp64_run"]["ms_per_sweep"] / out[f"{main_p}_run"]["ms_per_sweep"]
+    vo = vs_oracle(res, wl, args)
+    if vo:
+        out.setdefault("parity", {})["vs_oracle"] = vo
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out))

@@ -121,6 +121,20 @@ typedef struct dmrg_sweep_stats {
     int64_t kept_max;                  /* most block states kept by a truncation of the sweep */
     double energy_excited;             /* n_states = 2: lowest step energy of the second state (MeV) */
     double measure_seconds;            /* measure = 1: host wall time of the correlation measurements */
+    /* heff_flops counts, per product, for every term and psi block the
+     * cheaper of the two contraction orders (op(A) psi first, or psi op(B)^T
+     * first) over the nonzero sub-sector blocks of the operators, with true
+     * block dimensions and each intermediate formed once.  The kernels run the
+     * psi op(B)^T-first order; heff_flops_executed is what they multiply over
+     * columns that can be nonzero, and gemm{1,2}_flops split it by phase.
+     * gemm{1,2}_issued_flops also count the cleared columns that phase 2
+     * multiplies when it spans an output block's full width. */
+    double heff_flops_executed;
+    double gemm1_issued_flops, gemm2_issued_flops;
+    /* dmrg_check_fp64 on: solves repeated in FP64 from the same guess, and the
+     * largest |theta - theta_fp64| / |theta_fp64| over them */
+    int64_t check_solves;
+    double check_max_rel;
 } dmrg_sweep_stats;
 
 typedef struct dmrg_ctx dmrg_ctx;
@@ -176,6 +190,16 @@ dmrg_status dmrg_heff_layout(dmrg_ctx* ctx, int32_t* bond, int64_t* dim, int32_t
  * Asynchronous on the context stream; synchronise the stream before reading.
  * DMRG_ERR_STATE before the first sweep step. */
 dmrg_status dmrg_heff_apply(dmrg_ctx* ctx, const double* psi_in, double* psi_out, int32_t precision);
+
+/* Diagnostic for the mixed modes (the FP64 residual correction).  While
+ * `on` is 1, every Davidson solve of a mixed-precision context is repeated
+ * from the same guess with FP64 products only, on the same H_eff; the repeat's
+ * vector is discarded, so the run continues exactly as without the check.
+ * The sweep statistics then report the number of such pairs (check_solves)
+ * and the largest relative difference of their energies (check_max_rel).
+ * The repeats add device time to the sweep (not to heff_seconds).  Ignored
+ * in DMRG_FP64 mode.  Errors: ARG for `on` other than 0 or 1. */
+dmrg_status dmrg_check_fp64(dmrg_ctx* ctx, int32_t on);
 
 /* FP64 sweep energy (MeV) of the last completed sweep.  DMRG_ERR_STATE before. */
 dmrg_status dmrg_energy(dmrg_ctx* ctx, double* E);

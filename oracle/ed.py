@@ -188,3 +188,37 @@ def apply_rows(eps, V, configs: np.ndarray, psi: np.ndarray, rows: Iterable[int]
                         acc += v * s1 * s2 * s3 * s4 * psi[x]
         out.append(acc)
     return np.array(out)
+
+
+def abs_apply_rows(eps, V, configs: np.ndarray, psi: np.ndarray, rows: Iterable[int]) -> np.ndarray:
+    """Sum over the Slater-Condon terms of row r of |term| |psi|:
+    |psi_r| sum_{i occupied} |eps_i| plus |Vbar_ijkl| |psi_x| for every term
+    c+_i c+_j c_l c_k that connects the determinant of row r with component x.
+    This bounds (|H| |psi|)_r from above (equal where every matrix element is
+    a single term); it sets the scale of rounding errors in a product H psi
+    computed in reduced precision."""
+    eps = np.asarray(eps)
+    n = len(eps)
+    index = {int(c): x for x, c in enumerate(configs)}
+    by_kl: Dict[Tuple[int, int], List[Tuple[int, int, float]]] = {}
+    for (i, j, k, l, v) in _nonzero_two_body(V):
+        by_kl.setdefault((k, l), []).append((i, j, abs(v)))
+    out = []
+    for r in rows:
+        c = int(configs[r])
+        occ = [i for i in range(n) if (c >> i) & 1]
+        acc = abs(psi[r]) * sum(abs(eps[i]) for i in occ)
+        for a in range(len(occ)):
+            for b in range(a + 1, len(occ)):
+                lst = by_kl.get((occ[a], occ[b]))
+                if not lst:
+                    continue
+                c2 = c ^ (1 << occ[a]) ^ (1 << occ[b])
+                for (i, j, v) in lst:
+                    if (c2 >> i) & 1 or (c2 >> j) & 1:
+                        continue
+                    x = index.get(c2 | (1 << i) | (1 << j))
+                    if x is not None:
+                        acc += v * abs(psi[x])
+        out.append(acc)
+    return np.array(out)

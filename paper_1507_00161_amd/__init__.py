@@ -51,7 +51,10 @@ class SweepStats(ctypes.Structure):
                 ("gemm1_flops", ctypes.c_double), ("gemm2_flops", ctypes.c_double),
                 ("gemm1_bytes", ctypes.c_double), ("gemm2_bytes", ctypes.c_double),
                 ("reduce_seconds", ctypes.c_double), ("kept_max", ctypes.c_int64),
-                ("energy_excited", ctypes.c_double), ("measure_seconds", ctypes.c_double)]
+                ("energy_excited", ctypes.c_double), ("measure_seconds", ctypes.c_double),
+                ("heff_flops_executed", ctypes.c_double),
+                ("gemm1_issued_flops", ctypes.c_double), ("gemm2_issued_flops", ctypes.c_double),
+                ("check_solves", ctypes.c_int64), ("check_max_rel", ctypes.c_double)]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -75,6 +78,7 @@ def declare(lib: ctypes.CDLL) -> ctypes.CDLL:
         "dmrg_sweep_steps": (I32, [P, P, I32, I32, ctypes.POINTER(SweepStats)]),
         "dmrg_heff_layout": (I32, [P, ctypes.POINTER(I32), ctypes.POINTER(I64), ctypes.POINTER(I32), P, P]),
         "dmrg_heff_apply": (I32, [P, P, P, I32]),
+        "dmrg_check_fp64": (I32, [P, I32]),
         "dmrg_energy": (I32, [P, ctypes.POINTER(D)]),
         "dmrg_get_psi": (I32, [P, P]),
         "dmrg_heff_configs": (I32, [P, P]),
@@ -213,6 +217,11 @@ class Context:
         """y = H_eff x on the context stream (device pointers or torch tensors)."""
         self._check(self._lib.dmrg_heff_apply(self._h, ctypes.c_void_p(_dev_ptr(x)),
                                               ctypes.c_void_p(_dev_ptr(y)), precision))
+
+    def check_fp64(self, on: bool) -> None:
+        """Repeat every mixed-precision solve in FP64 from the same guess and
+        report the largest energy difference (dmrg_check_fp64)."""
+        self._check(self._lib.dmrg_check_fp64(self._h, 1 if on else 0))
 
     def energy(self) -> float:
         e = ctypes.c_double()

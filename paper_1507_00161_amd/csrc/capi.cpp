@@ -127,6 +127,15 @@ dmrg_status dmrg_heff_apply(dmrg_ctx* c, const double* x, double* y, int32_t pre
     return guarded(c, [&] { return c->eng->apply(x, y, precision); });
 }
 
+dmrg_status dmrg_check_fp64(dmrg_ctx* c, int32_t on) {
+    if (!c) return DMRG_ERR_ARG;
+    if (on != 0 && on != 1) {
+        c->err = "on must be 0 or 1";
+        return DMRG_ERR_ARG;
+    }
+    return guarded(c, [&] { return c->eng->set_check_fp64(on != 0); });
+}
+
 dmrg_status dmrg_energy(dmrg_ctx* c, double* E) {
     return guarded(c, [&] { return c->eng->energy(E); });
 }

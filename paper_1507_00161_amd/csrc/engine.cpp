@@ -181,8 +181,11 @@ struct GB {
     };
     std::vector<OB> obs;
     std::vector<GemmChunk> chunks;
+    // per chunk: output columns that can be nonzero (the rest of the block's
+    // width is multiplied by cleared operand columns); empty = all
+    std::vector<int> nuse;
     int64_t cb = 0;
-    double flops = 0.0, elems = 0.0;
+    double flops = 0.0, issued = 0.0, elems = 0.0;
     void begin() { cb = (int64_t)chunks.size(); }
     void chunk(double alpha, int abuf, int64_t aoff, int lda, bool atr, int bbuf, int64_t boff, int ldb,
                bool btr, int K) {
@@ -202,8 +205,10 @@ struct GB {
     void end(int cbuf, int64_t coff, int ldc, int M, int Nn, int beta) {
         int64_t ce = (int64_t)chunks.size();
         for (int64_t x = cb; x < ce; ++x) {
-            flops += 2.0 * M * Nn * chunks[x].K;
-            elems += (double)chunks[x].K * (M + Nn);
+            const int nu = x < (int64_t)nuse.size() ? nuse[x] : Nn;
+            flops += 2.0 * M * nu * chunks[x].K;
+            issued += 2.0 * M * Nn * chunks[x].K;
+            elems += (double)chunks[x].K * (M + nu);
         }
         elems += (double)M * Nn * (beta ? 2 : 1);
         obs.push_back({cbuf, coff, ldc, M, Nn, beta, cb, ce});
@@ -473,6 +478,7 @@ static void plan_host(const GB& g, GemmPlan& p, PlanHost& h) {
     p.nslots = slot;
     p.nchunks = (int64_t)g.chunks.size();
     p.flops = g.flops;
+    p.issued = g.issued;
     p.elems = g.elems;
 }
 
@@ -1451,8 +1457,10 @@ dmrg_status Engine::build_heff_plan(Bond& B) {
     struct TermWork {
         std::vector<ZOut> z;
         std::vector<std::pair<int, GemmChunk>> c2;   // (yid, chunk); Z offsets relative
+        std::vector<int> n2;                         // per c2 chunk: columns that can be nonzero
         std::vector<std::pair<int, GemmChunk>> c3;   // (subid, chunk) of the E-only term
         int64_t zsize = 0;
+        double alg = 0.0;                            // algorithmic flops
     };
     auto leaves = [&]() { return fail(DMRG_ERR_DEVICE, "internal: H_eff term leaves the target sector"); };
     auto work = [&](const Term& tm, TermWork& w) -> dmrg_status {
@@ -1466,12 +1474,49 @@ dmrg_status Engine::build_heff_plan(Bond& B) {
         for (int x = 0; x < nb; ++x) {
             const int mS = B.pm_S[x], mE = B.pm_E[x];
             const int ldx = E.md[mE];
+            // Algorithmic flops of the term on this block: the cheaper of the two
+            // contraction orders, over the nonzero sub-sector blocks (A: i -> i2,
+            // B: j -> j2) with each intermediate formed once:
+            //   B first: 2 (sum_{i acted on} d_i) sum_B d_j d_j2 + 2 sum_A d_i d_i2 (sum_{j2 reached} d_j2)
+            //   A first: 2 sum_A d_i d_i2 (sum_{j acted on} d_j) + 2 (sum_{i2 reached} d_i2) sum_B d_j d_j2
+            {
+                double sa = 0.0, sb = 0.0, din = 0.0, dout = 0.0, ein = 0.0, eout = 0.0;
+                if (A) {
+                    std::set<int> i_out;
+                    for (int i : S.msub[mS]) {
+                        if (i < 0 || A->acting(i, tm.ta).empty()) continue;
+                        din += S.sub[i].dim;
+                        for (int ai : A->acting(i, tm.ta)) {
+                            const int i2 = tm.ta ? A->blk[ai].in : A->blk[ai].out;
+                            sa += (double)S.sub[i].dim * S.sub[i2].dim;
+                            i_out.insert(i2);
+                        }
+                    }
+                    for (int i2 : i_out) dout += S.sub[i2].dim;
+                }
+                if (Bo) {
+                    std::set<int> j_out;
+                    for (int j : E.msub[mE]) {
+                        if (j < 0 || Bo->acting(j, tm.tb).empty()) continue;
+                        ein += E.sub[j].dim;
+                        for (int bi : Bo->acting(j, tm.tb)) {
+                            const int j2 = tm.tb ? Bo->blk[bi].in : Bo->blk[bi].out;
+                            sb += (double)E.sub[j].dim * E.sub[j2].dim;
+                            j_out.insert(j2);
+                        }
+                    }
+                    for (int j2 : j_out) eout += E.sub[j2].dim;
+                }
+                if (A && Bo) w.alg += 2.0 * std::min(din * sb + sa * eout, sa * ein + dout * sb);
+                else if (A) w.alg += 2.0 * sa * ldx;
+                else if (Bo) w.alg += 2.0 * S.md[mS] * sb;
+            }
             // When the S operator acts on every sub-sector of this block, Z_t for
             // the whole block (all its rows) is formed at once: taller phase-1
             // output blocks, one operator read per block row tile.
             bool zrow_done = false;
             int64_t zrow = 0;
-            int NE2x = 0;
+            int NE2x = 0, NE2use = 0;
             if (A && Bo) {
                 bool all = true;
                 for (int i : S.msub[mS])
@@ -1490,6 +1535,9 @@ dmrg_status Engine::build_heff_plan(Bond& B) {
                 }
                 if (all && m2 >= 0) {
                     NE2x = E.md[m2];
+                    NE2use = 0;
+                    for (int j2 : E.msub[m2])
+                        if (j2 >= 0 && !fd[E.sub[j2].sigma].empty()) NE2use += E.sub[j2].dim;
                     const int dS = S.md[mS];
                     zrow = w.zsize;
                     w.zsize += ((int64_t)dS * NE2x + 7) / 8 * 8;
@@ -1524,9 +1572,12 @@ dmrg_status Engine::build_heff_plan(Bond& B) {
                         if (x2 < 0 || B.pm_E[x2] != mE) return leaves();
                         w.c2.push_back({yid(x2, i2), GemmChunk{alpha_of(i, i2), ab.off, xrow, ab.cols, ldx, di, 0, 2,
                                                                (uint8_t)tm.ta, 0}});
+                        w.n2.push_back(ldx);
                     }
                     continue;
                 }
+                // no S block on this sub-sector: no Z row block is needed
+                if (A && A->acting(i, tm.ta).empty()) continue;
                 // E operator: which input sub-sectors j feed which output sub-sector j2
                 std::vector<std::pair<int, int>> feeds[2];   // per output sigma: (j, block)
                 int mE2 = -1;
@@ -1564,7 +1615,11 @@ dmrg_status Engine::build_heff_plan(Bond& B) {
                     w.zsize += ((int64_t)di * E.md[mE2] + 7) / 8 * 8;
                 }
                 const int NE2 = E.md[mE2];
+                int use = NE2x ? NE2use : 0;
                 if (!zrow_done) {
+                    use = 0;
+                    for (int j2 : E.msub[mE2])
+                        if (j2 >= 0 && !feeds[E.sub[j2].sigma].empty()) use += E.sub[j2].dim;
                     for (int j2 : E.msub[mE2]) {
                         if (j2 < 0) continue;
                         ZOut out;
@@ -1588,6 +1643,7 @@ dmrg_status Engine::build_heff_plan(Bond& B) {
                     if (x2 < 0 || B.pm_E[x2] != mE2) return leaves();
                     w.c2.push_back(
                         {yid(x2, i2), GemmChunk{alpha_of(i, i2), ab.off, zo, ab.cols, NE2, di, 0, 3, (uint8_t)tm.ta, 0}});
+                    w.n2.push_back(use);
                 }
             }
         }
@@ -1596,7 +1652,9 @@ dmrg_status Engine::build_heff_plan(Bond& B) {
 
     B.groups.clear();
     B.flops = 0.0;
+    B.flops_alg = 0.0;
     std::vector<std::vector<GemmChunk>> lists(nb * 2), lists3(nb * 4);
+    std::vector<std::vector<int>> lists_n(nb * 2);
     GB g1;
     int64_t z = 0;
     bool first = true;
@@ -1611,9 +1669,11 @@ dmrg_status Engine::build_heff_plan(Bond& B) {
             if (!first && l.empty()) continue;
             g2.begin();
             g2.chunks.insert(g2.chunks.end(), l.begin(), l.end());
+            g2.nuse.insert(g2.nuse.end(), lists_n[id].begin(), lists_n[id].end());
             const int ldy = E.md[B.pm_E[x]];
             g2.end(4, B.poff[x] + (int64_t)S.sub[i2].off * ldy, ldy, S.sub[i2].dim, ldy, first ? 0 : 1);
             l.clear();
+            lists_n[id].clear();
         }
         for (int id = 0; id < nb * 4; ++id) {
             auto& l = lists3[id];
@@ -1649,11 +1709,13 @@ dmrg_status Engine::build_heff_plan(Bond& B) {
             g1.chunks.insert(g1.chunks.end(), zb.chunks.begin(), zb.chunks.end());
             g1.end(3, z + zb.zoff, zb.ldz, zb.M, zb.N, 0);
         }
-        for (auto& pc : w.c2) {
-            GemmChunk c = pc.second;
+        for (size_t q = 0; q < w.c2.size(); ++q) {
+            GemmChunk c = w.c2[q].second;
             if (c.b_buf == 3) c.b_off += z;
-            lists[pc.first].push_back(c);
+            lists[w.c2[q].first].push_back(c);
+            lists_n[w.c2[q].first].push_back(w.n2[q]);
         }
+        B.flops_alg += w.alg;
         for (auto& pc : w.c3) lists3[pc.first].push_back(pc.second);
         z += w.zsize;
     }
@@ -1795,12 +1857,14 @@ void Engine::account(const HeffGroup& g, double es1, double es2) {
         acc_.gemm1_launches += 1;
         acc_.gemm1_seconds += t1;
         acc_.gemm1_flops += g.p1.flops;
+        acc_.gemm1_issued_flops += g.p1.issued;
         acc_.gemm1_bytes += g.p1.elems * es1;
     }
     if (g.p2.ntasks) {
         acc_.gemm2_launches += 1;
         acc_.gemm2_seconds += t2;
         acc_.gemm2_flops += g.p2.flops;
+        acc_.gemm2_issued_flops += g.p2.issued;
         acc_.gemm2_bytes += g.p2.elems * es2;
     }
 }
@@ -1850,7 +1914,8 @@ dmrg_status Engine::davidson(Bond& B, Buf& psi, const double* lock, double* thet
     double* sc = s + 32;                // scalars: 0 theta, 1 |r|^2, 2 |t|^2, 3 |x|^2
     double* cc = sc + 8;                // 32 (projection coefficients)
     const int ldg = 32;
-    const int lowp = opt_.precision == DMRG_MIXED_FP32 ? dmrgdev::P_F32
+    const int lowp = force_fp64_ ? dmrgdev::P_F64
+                     : opt_.precision == DMRG_MIXED_FP32 ? dmrgdev::P_F32
                      : opt_.precision == DMRG_MIXED_BF16 ? dmrgdev::P_BF16 : dmrgdev::P_F64;
     const bool mixed = lowp != dmrgdev::P_F64;
     const int max_refresh = 8;
@@ -1982,6 +2047,15 @@ dmrg_status Engine::davidson(Bond& B, Buf& psi, const double* lock, double* thet
     // psi <- x normalised
     DEV(dmrgdev::dots(dev_, dv_x_.d(), 0, 1, dv_x_.d(), n, sc + 3));
     DEV(dmrgdev::copy_scaled_inv_norm(dev_, dv_x_.d(), n, sc + 3, psi.d()));
+    if (!exact) {
+        // Stopped (product limit or stagnation) with reduced-precision
+        // columns in the subspace: theta is then not an FP64 quantity.  One
+        // more FP64 product gives the Rayleigh quotient of the returned vector.
+        TRY(heff(B, psi.d(), Wm, dmrgdev::P_F64));
+        *n64 += 1;
+        DEV(dmrgdev::dots(dev_, psi.d(), 0, 1, Wm, n, sc));
+        DEV(dmrgdev::d2h(dev_, &theta, sc, sizeof(double)));
+    }
     *theta_out = theta;
     return DMRG_OK;
 }
@@ -2602,10 +2676,27 @@ dmrg_status Engine::steps(const int32_t* ordering, int D, int64_t max_steps, boo
             double th;
             int64_t nlo, n64;
             bool conv;
+            const bool check = check_fp64_ && opt_.precision != DMRG_FP64;
+            if (check) {   // the guess, for the FP64 repeat
+                TRY(alloc_buf(chk_psi_, std::max<int64_t>(cur_->dim, 1) * sizeof(double)));
+                DEV(dmrgdev::d2d(dev_, chk_psi_.p, psi_.p, cur_->dim * sizeof(double)));
+            }
             heff_time_ = 0.0;
             TRY(davidson(*cur_, psi_, nullptr, &th, &nlo, &n64, &conv));
             acc_.heff_seconds += heff_time_;
-            acc_.heff_flops += cur_->flops * (double)(nlo + n64);
+            acc_.heff_flops += cur_->flops_alg * (double)(nlo + n64);
+            acc_.heff_flops_executed += cur_->flops * (double)(nlo + n64);
+            if (check) {
+                double th64;
+                int64_t a, c;
+                bool cv;
+                force_fp64_ = true;
+                dmrg_status cs = davidson(*cur_, chk_psi_, nullptr, &th64, &a, &c, &cv);
+                force_fp64_ = false;
+                TRY(cs);
+                acc_.check_solves += 1;
+                acc_.check_max_rel = std::max(acc_.check_max_rel, std::fabs(th - th64) / std::fabs(th64));
+            }
             acc_.products_low += nlo;
             acc_.products_fp64 += n64;
             acc_.solves += 1;
@@ -2618,7 +2709,8 @@ dmrg_status Engine::steps(const int32_t* ordering, int D, int64_t max_steps, boo
                 heff_time_ = 0.0;
                 TRY(davidson(*cur_, psi1_, psi_.d(), &th, &nlo, &n64, &conv));
                 acc_.heff_seconds += heff_time_;
-                acc_.heff_flops += cur_->flops * (double)(nlo + n64);
+                acc_.heff_flops += cur_->flops_alg * (double)(nlo + n64);
+                acc_.heff_flops_executed += cur_->flops * (double)(nlo + n64);
                 acc_.products_low += nlo;
                 acc_.products_fp64 += n64;
                 acc_.solves += 1;

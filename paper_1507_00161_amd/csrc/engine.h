@@ -219,7 +219,8 @@ struct GemmPlan {
     int nwg = 0, nfull = 0;   // persistent work-groups; tasks with chunks
     int64_t nslots = 0;     // split-K partial tiles
     int64_t nchunks = 0;
-    double flops = 0.0;
+    double flops = 0.0;    // useful: 2 M N K per chunk over the columns that can be nonzero
+    double issued = 0.0;   // 2 M N K per chunk over the whole output block width
     double elems = 0.0;    // operand elements read + result elements written (algorithmic)
 };
 
@@ -240,7 +241,8 @@ struct Bond {
     int64_t dim = 0;
     std::vector<Term> terms;
     std::vector<HeffGroup> groups;
-    double flops = 0.0;
+    double flops = 0.0;       // useful flops of the launches of one product
+    double flops_alg = 0.0;   // algorithmic flops of one product (cheaper contraction order)
     Buf diag;
     int lo_prec = -1;
 };
@@ -263,6 +265,10 @@ public:
     dmrg_status configs(uint64_t* out);
     dmrg_status orbital_entropies(double* s1, double* mutual, double* n1, double* nn, double* hop);
     bool measuring() const { return opt_.measure != 0; }
+    dmrg_status set_check_fp64(bool on) {
+        check_fp64_ = on;
+        return DMRG_OK;
+    }
 
     const std::string& error() const { return err_; }
     dmrg_status fail(dmrg_status s, const std::string& msg) {
@@ -339,6 +345,9 @@ private:
     // scratch
     Buf z_, xlo_, ylo_, scr_a_, scr_b_, scal_;
     double heff_time_ = 0.0;   // device seconds of H_eff products in the current solve
+    bool check_fp64_ = false;  // repeat mixed solves in FP64 (diagnostic)
+    bool force_fp64_ = false;  // the solve in progress uses FP64 products only
+    Buf chk_psi_;              // guess kept for the repeat
 
     bool reachable(const Reach& r, const QN& q) const;
     Reach make_reach(int a, int b) const;

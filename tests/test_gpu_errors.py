@@ -143,3 +143,11 @@ def test_memory_cap_reports_out_of_memory(pk):
     assert e.value.status == -5
     # the context is still usable for a fresh load
     _load(c, _h())
+
+
+def test_check_fp64_rejects_bad_argument(pk):
+    c = pk.Context(precision=1)
+    assert c._lib.dmrg_check_fp64(c._h, 2) == -1
+    assert c._lib.dmrg_check_fp64(None, 1) == -1
+    c.check_fp64(True)
+    c.check_fp64(False)

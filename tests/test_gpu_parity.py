@@ -62,6 +62,29 @@ def _chain(h, order):
     return h.eps[order], h.V[np.ix_(order, order, order, order)]
 
 
+# Element-wise bounds of the reduced-precision products.  With u the unit
+# roundoff of the operand type (2^-24 FP32, 2^-8 BF16), a product of an
+# operator entry, a psi entry and a second operator entry picks up at most
+# five roundings of relative size u/2 (psi, both operators, the alpha scaling
+# and the intermediate Z), so the input part of the error of output row r is
+# at most 2.5 u S_r, S_r = sum over the row's Slater-Condon terms of
+# |term| |x| (ed.abs_apply_rows, >= (|H||x|)_r), since every GEMM product is
+# bounded by one such term in a determinant basis.  FP32 accumulation adds
+# roundings of the running sums; these are sums of terms of both signs, and
+# their rounding errors stay of the order of u S_r.  The bounds below are
+# c u S_r with c = 4 (BF16: inputs only; its FP32 accumulation is 2^16 finer)
+# and c = 64 (FP32: inputs plus accumulation, with a wide margin).
+U_LOW = {1: 2.0 ** -24, 2: 2.0 ** -8}
+C_LOW = {1: 64.0, 2: 4.0}
+
+
+def _check_low(y_low, ref, scale, prec):
+    err = np.abs(y_low - ref)
+    bound = C_LOW[prec] * U_LOW[prec] * scale + 1e-300
+    assert np.all(err <= bound), (prec, float((err / bound).max()))
+    return float((err / (U_LOW[prec] * np.maximum(scale, 1e-300))).max())
+
+
 @pytest.mark.parametrize("space,n_p,n_n,two_M,D,rand", [
     ("p", 2, 2, 0, 6, False),
     ("sd", 2, 3, 1, 10, True),
@@ -87,6 +110,9 @@ def test_heff_equals_slater_condon_every_bond(pk, torch_dev, space, n_p, n_n, tw
         rows = np.arange(dim) if dim <= 300 else rng.choice(dim, 300, replace=False)
         ref = ed.apply_rows(eps_c, V_c, cfg, x, rows)
         worst = max(worst, np.abs(y[rows] - ref).max() / max(1.0, np.abs(ref).max()))
+        scale = ed.abs_apply_rows(eps_c, V_c, cfg, x, rows)
+        for prec in (1, 2):
+            _check_low(_apply(c, x, torch_dev, prec)[rows], ref, scale, prec)
     assert worst < 1e-12
 
 
@@ -105,10 +131,9 @@ def test_heff_full_size_pf_8p8n_D2048_sampled_rows(pk, torch_dev):
     ref = ed.apply_rows(h.eps, h.V, cfg, x, rows)
     y64 = _apply(c, x, torch_dev, 0)
     assert np.abs(y64[rows] - ref).max() < 1e-11 * max(1.0, np.abs(ref).max())
-    y32 = _apply(c, x, torch_dev, 1)
-    assert np.linalg.norm(y32 - y64) < 1e-5 * np.linalg.norm(y64)
-    y16 = _apply(c, x, torch_dev, 2)
-    assert np.linalg.norm(y16 - y64) < 2e-2 * np.linalg.norm(y64)
+    scale = ed.abs_apply_rows(h.eps, h.V, cfg, x, rows)
+    for prec in (1, 2):
+        _check_low(_apply(c, x, torch_dev, prec)[rows], ref, scale, prec)
 
 
 @pytest.mark.parametrize("name,D", [("pfg9_12p12n", 2048), ("pfg9_12p12n_M2", 1024)])
@@ -128,8 +153,9 @@ def test_heff_full_size_pfg9_sampled_rows(pk, torch_dev, name, D):
     ref = ed.apply_rows(h.eps, h.V, cfg, x, rows)
     y64 = _apply(c, x, torch_dev, 0)
     assert np.abs(y64[rows] - ref).max() < 1e-11 * max(1.0, np.abs(ref).max())
-    y32 = _apply(c, x, torch_dev, 1)
-    assert np.linalg.norm(y32 - y64) < 1e-5 * np.linalg.norm(y64)
+    scale = ed.abs_apply_rows(h.eps, h.V, cfg, x, rows)
+    for prec in (1, 2):
+        _check_low(_apply(c, x, torch_dev, prec)[rows], ref, scale, prec)
 
 
 def test_heff_is_symmetric_and_linear(pk, torch_dev):
@@ -144,6 +170,42 @@ def test_heff_is_symmetric_and_linear(pk, torch_dev):
     assert abs(x2 @ y1 - x1 @ y2) < 1e-11 * abs(x2 @ y1) + 1e-11
     y12 = _apply(c, 2.0 * x1 - 3.0 * x2, torch_dev)
     assert np.abs(y12 - (2 * y1 - 3 * y2)).max() < 1e-11 * np.abs(y12).max()
+
+
+@pytest.mark.parametrize("precision", [1, 2])
+def test_mixed_davidson_at_the_product_limit_returns_the_fp64_rayleigh_quotient(pk, torch_dev, precision):
+    """A mixed solve stopped by davidson_max_iter with reduced-precision
+    columns in its subspace still reports the FP64 Rayleigh quotient of the
+    vector it returns.  The state at the turning point (bond N - 2) is the
+    solve's own result, so theta = psi . H64 psi there."""
+    h = WORKLOADS["sd_4p4n"].hamiltonian()
+    c = _ctx(pk, h, precision=precision, davidson_tol=1e-12, davidson_max_iter=3, seed=4)
+    r = c.sweep_steps(64, h.space.n_sites - 1)
+    assert r["code"] == 1 and r["not_converged"] > 0
+    bond, dim, _, _ = c.heff_layout()
+    assert bond == h.space.n_sites - 2
+    psi = c.get_psi()
+    assert abs(psi @ psi - 1.0) < 1e-12
+    th = psi @ _apply(c, psi, torch_dev, 0)
+    assert abs(r["last_theta"] - th) <= 1e-13 * abs(th), (r["last_theta"], th)
+
+
+@pytest.mark.parametrize("name,D", [("sd_4p4n", 48), ("pf_8p8n", 64)])
+def test_fp64_check_leaves_the_run_unchanged(pk, name, D):
+    """dmrg_check_fp64 repeats every mixed solve in FP64 from the same guess:
+    the energies of the run are bit-identical to a run without it, every solve
+    is paired, and the paired energies agree within the mixed tolerance."""
+    h = WORKLOADS[name].hamiltonian()
+    opts = dict(precision=1, davidson_tol=1e-7, noise=1e-4, noise_sweeps=1, seed=5)
+    a, b = _ctx(pk, h, **opts), _ctx(pk, h, **opts)
+    b.check_fp64(True)
+    for _ in range(2):
+        ra, rb = a.sweep(D), b.sweep(D)
+        assert ra["energy"] == rb["energy"] and ra["last_theta"] == rb["last_theta"]
+        assert ra["check_solves"] == 0 and rb["check_solves"] == rb["solves"] > 0
+        assert rb["check_max_rel"] <= 1e-6
+    b.check_fp64(False)
+    assert b.sweep(D)["check_solves"] == 0
 
 
 def _golden():

@@ -141,6 +141,31 @@ def test_ed_apply_rows_matches_matrix():
     assert np.allclose(ed.apply_rows(h.eps, h.V, basis, psi, rows), (H @ psi)[rows], atol=1e-12)
 
 
+def test_ed_abs_apply_rows_bounds_abs_matrix():
+    """abs_apply_rows >= |H| |psi| row by row (from the sparse matrix), with
+    equality for one proton and one neutron, where every off-diagonal element
+    is a single Vbar and the diagonal is eps_i + eps_j + Vbar_ijij."""
+    space = _small_space()
+    for target, equal in (((2, 2, 0), False), ((1, 1, 0), True)):
+        h = make_hamiltonian(space, 6, *target)
+        basis = ed.mscheme_basis(space.species, space.two_m, *target)
+        H = ed.hamiltonian_matrix(h.eps, h.V, basis)
+        psi = np.random.default_rng(2).normal(size=len(basis))
+        rows = range(len(basis))
+        ref = abs(H) @ np.abs(psi)
+        got = ed.abs_apply_rows(h.eps, h.V, basis, psi, rows)
+        assert np.all(got >= ref - 1e-12)
+        if equal:
+            # the diagonal may cancel between eps and Vbar_ijij: compare off it
+            off = abs(H - sp.diags(H.diagonal())) @ np.abs(psi)
+            dia = np.abs(psi) * np.array([abs(h.eps[i]) + abs(h.eps[j]) + abs(h.V[i, j, i, j])
+                                          for i, j in (sorted(b for b in range(8) if (int(c) >> b) & 1)
+                                                       for c in basis)])
+            assert np.allclose(got, off + dia, rtol=0, atol=1e-12)
+        else:
+            assert np.any(got > ref + 1e-9)      # one-body-like elements add several terms
+
+
 # ---------------------------------------------------------- closed forms
 def _pairing_energy(eps0, G, space, n_p, n_n):
     omega = int(np.sum(space.species == 0)) // 2
