@@ -191,6 +191,22 @@ dmrg_status dmrg_heff_layout(dmrg_ctx* ctx, int32_t* bond, int64_t* dim, int32_t
  * DMRG_ERR_STATE before the first sweep step. */
 dmrg_status dmrg_heff_apply(dmrg_ctx* ctx, const double* psi_in, double* psi_out, int32_t precision);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * product as dmrg_heff_apply (same plans, kernels and launch order, so the
+ * same result), with every intermediate in a fixed device array of 64 MiB
+ * that the library holds on each GPU it runs on until the process ends:
+ * the reduced-precision operator copies (converted on every call), the
+ * reduced-precision input and output, the intermediate psi op(B)^T and the
+ * split-K partial tiles.  No device memory is allocated or freed.  A bond
+ * whose intermediates exceed the array returns DMRG_ERR_OUT_OF_MEMORY (with
+ * the size needed in dmrg_last_error) and launches nothing.  All calls on a
+ * GPU share its array and nothing is carried from one call to the next:
+ * calls whose streams can overlap on one GPU (two contexts with different
+ * streams) race and must be ordered by the caller.  Arguments, layout and
+ * other errors as for dmrg_heff_apply; asynchronous on the context stream. */
+dmrg_status dmrg_heff_apply_noalloc(dmrg_ctx* ctx, const double* psi_in, double* psi_out, int32_t precision);
+
 /* Diagnostic for the mixed modes (the FP64 residual correction).  While
  * `on` is 1, every Davidson solve of a mixed-precision context is repeated
  * from the same guess with FP64 products only, on the same H_eff; the repeat's

@@ -79,6 +79,7 @@ def declare(lib: ctypes.CDLL) -> ctypes.CDLL:
         "dmrg_heff_layout": (I32, [P, ctypes.POINTER(I32), ctypes.POINTER(I64), ctypes.POINTER(I32), P, P]),
         "dmrg_heff_apply": (I32, [P, P, P, I32]),
         "dmrg_check_fp64": (I32, [P, I32]),
+        "dmrg_heff_apply_noalloc": (I32, [P, P, P, I32]),
         "dmrg_energy": (I32, [P, ctypes.POINTER(D)]),
         "dmrg_get_psi": (I32, [P, P]),
         "dmrg_heff_configs": (I32, [P, P]),
@@ -217,6 +218,11 @@ class Context:
         """y = H_eff x on the context stream (device pointers or torch tensors)."""
         self._check(self._lib.dmrg_heff_apply(self._h, ctypes.c_void_p(_dev_ptr(x)),
                                               ctypes.c_void_p(_dev_ptr(y)), precision))
+
+    def heff_apply_noalloc(self, x, y, precision: int = FP64) -> None:
+        """y = H_eff x with the library's fixed device scratch (dmrg_heff_apply_noalloc)."""
+        self._check(self._lib.dmrg_heff_apply_noalloc(self._h, ctypes.c_void_p(_dev_ptr(x)),
+                                                      ctypes.c_void_p(_dev_ptr(y)), precision))
 
     def check_fp64(self, on: bool) -> None:
         """Repeat every mixed-precision solve in FP64 from the same guess and

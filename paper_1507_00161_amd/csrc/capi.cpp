@@ -127,6 +127,10 @@ dmrg_status dmrg_heff_apply(dmrg_ctx* c, const double* x, double* y, int32_t pre
     return guarded(c, [&] { return c->eng->apply(x, y, precision); });
 }
 
+dmrg_status dmrg_heff_apply_noalloc(dmrg_ctx* c, const double* x, double* y, int32_t precision) {
+    return guarded(c, [&] { return c->eng->apply_static(x, y, precision); });
+}
+
 dmrg_status dmrg_check_fp64(dmrg_ctx* c, int32_t on) {
     if (!c) return DMRG_ERR_ARG;
     if (on != 0 && on != 1) {

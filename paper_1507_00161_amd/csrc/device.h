@@ -33,6 +33,13 @@ int sync(Ctx* c);
 // Make the context's device current on the calling host thread.
 int bind(Ctx* c);
 
+// Static device scratch (no allocation): the device address of this
+// device's fixed array of kStaticScratchBytes, resolved when the context was
+// created.  Shared by every context on the device; its contents persist
+// between uses.
+constexpr size_t kStaticScratchBytes = (size_t)64 << 20;
+void* static_scratch(Ctx* c, size_t* bytes);
+
 // timing on the context stream
 int event_record(Ctx* c, int slot);                   // slot < 64
 double event_elapsed(Ctx* c, int slot0, int slot1);   // seconds, synchronises

@@ -16,12 +16,19 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
 #include "device.h"
 
 namespace dmrgdev {
+
+// Fixed device scratch for callers that cannot allocate (static_scratch):
+// every GPU the library runs on holds its own copy until the process ends.
+// Host code never uses the array's name as an address: its device address is
+// looked up once per device (scratch_addr) and used from there on.
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
 
 constexpr int kSide = 4;
 
@@ -50,6 +57,8 @@ struct Ctx {
     // pinned staging arena for stream-ordered uploads
     char* stage = nullptr;
     size_t stage_cap = 0, stage_off = 0;
+    // device address of this device's static scratch array
+    void* scratch = nullptr;
 };
 
 static int seterr(Ctx* c, const char* what, hipError_t e) {
@@ -102,8 +111,33 @@ int ctx_create(int device, void* stream, Ctx** out, char* err, size_t errlen) {
         return fail("hipMalloc failed");
     }
     c->info_cap = 1;
+    // device address of the static scratch on this device (with it current)
+    {
+        static std::mutex mu;
+        static void* addr[256] = {};
+        std::lock_guard<std::mutex> lock(mu);
+        if (device >= 256) {
+            ctx_destroy(c);
+            return fail("device ordinal above 255");
+        }
+        if (!addr[device]) {
+            void* p = nullptr;
+            hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+            if (e != hipSuccess || !p) {
+                ctx_destroy(c);
+                return fail("hipGetSymbolAddress of the static scratch failed");
+            }
+            addr[device] = p;
+        }
+        c->scratch = addr[device];
+    }
     *out = c;
     return 0;
+}
+
+void* static_scratch(Ctx* c, size_t* bytes) {
+    if (bytes) *bytes = kStaticScratchBytes;
+    return c->scratch;
 }
 
 void ctx_destroy(Ctx* c) {

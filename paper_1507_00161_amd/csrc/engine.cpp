@@ -215,15 +215,20 @@ struct GB {
     }
 };
 
-dmrg_status Engine::run_gemm(int prec, BufTable bufs, const GemmPlan& p, int cprec, int kind, int ev_mid) {
+dmrg_status Engine::run_gemm(int prec, BufTable bufs, const GemmPlan& p, int cprec, int kind, int ev_mid,
+                             void* partials) {
     if (cprec < 0) cprec = prec == dmrgdev::P_BF16 ? dmrgdev::P_F32 : prec;
     if (p.ntasks == 0) {
         if (ev_mid >= 0) DEV(dmrgdev::event_record(dev_, ev_mid));
         return DMRG_OK;
     }
     if (p.nslots) {
-        TRY(ensure_partials(p.nslots));
-        bufs[dmrgdev::kPartialBuf] = partial_.p;
+        if (partials) {
+            bufs[dmrgdev::kPartialBuf] = partials;
+        } else {
+            TRY(ensure_partials(p.nslots));
+            bufs[dmrgdev::kPartialBuf] = partial_.p;
+        }
     }
     dmrgdev::Sched sc;
     sc.wg_off = p.wg_off.as<int32_t>();
@@ -3033,6 +3038,68 @@ dmrg_status Engine::apply(const double* x, double* y, int prec) {
     if (!x || !y) return fail(DMRG_ERR_ARG, "null vector");
     if (prec < 0 || prec > 2) return fail(DMRG_ERR_ARG, "precision must be 0, 1 or 2");
     return heff_launch(*cur_, x, y, prec, false);
+}
+
+// y = H_eff x with every intermediate in the device's static scratch: the
+// reduced-precision operator copies (converted here on every call), the
+// reduced-precision x and y, Z and the split-K partial tiles.  No device
+// memory is allocated or freed.  The launches are those of apply().
+dmrg_status Engine::apply_static(const double* x, double* y, int prec) {
+    if (!cur_) return fail(DMRG_ERR_STATE, "no current bond (run a sweep first)");
+    if (!x || !y) return fail(DMRG_ERR_ARG, "null vector");
+    if (prec < 0 || prec > 2) return fail(DMRG_ERR_ARG, "precision must be 0, 1 or 2");
+    Bond& B = *cur_;
+    size_t cap = 0;
+    char* base = static_cast<char*>(dmrgdev::static_scratch(dev_, &cap));
+    if (!base) return fail(DMRG_ERR_DEVICE, "static scratch is not available on this device");
+    const bool low = prec != dmrgdev::P_F64;
+    const size_t es = prec == dmrgdev::P_F64 ? 8 : (prec == dmrgdev::P_F32 ? 4 : 2);
+    int64_t zmax = 0, slots = 0;
+    for (auto& g : B.groups) {
+        zmax = std::max(zmax, g.z_elems);
+        slots = std::max({slots, g.p1.nslots, g.p2.nslots, g.p3.nslots});
+    }
+    auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    size_t off = 0;
+    const size_t s_off = off;
+    if (low) off += al((size_t)B.Sops.size * es);
+    const size_t e_off = off;
+    if (low) off += al((size_t)B.Eops.size * es);
+    const size_t x_off = off;
+    if (low) off += al((size_t)B.dim * es);
+    const size_t y_off = off;
+    if (low) off += al((size_t)B.dim * 4);
+    const size_t z_off = off;
+    off += al((size_t)std::max<int64_t>(zmax, 1) * es);
+    const size_t p_off = off;
+    off += al((size_t)slots * dmrgdev::kTileM * dmrgdev::kTileN * sizeof(double));
+    if (off > cap) {
+        std::ostringstream m;
+        m << "this bond needs " << off << " bytes of static scratch; the array holds " << cap
+          << " (use dmrg_heff_apply)";
+        return fail(DMRG_ERR_OUT_OF_MEMORY, m.str());
+    }
+    void* part = slots ? base + p_off : nullptr;
+    if (!low) {
+        for (auto& g : B.groups) {
+            BufTable bufs{B.Sops.pool.p, B.Eops.pool.p, (void*)x, base + z_off, y};
+            TRY(run_gemm(prec, bufs, g.p1, -1, dmrgdev::GK_HEFF_Z, -1, part));
+            TRY(run_gemm(prec, bufs, g.p2, -1, dmrgdev::GK_HEFF_Y, -1, part));
+            TRY(run_gemm(prec, bufs, g.p3, -1, dmrgdev::GK_OTHER, -1, part));
+        }
+        return DMRG_OK;
+    }
+    DEV(dmrgdev::convert(dev_, dmrgdev::P_F64, B.Sops.pool.p, prec, base + s_off, B.Sops.size));
+    DEV(dmrgdev::convert(dev_, dmrgdev::P_F64, B.Eops.pool.p, prec, base + e_off, B.Eops.size));
+    DEV(dmrgdev::convert(dev_, dmrgdev::P_F64, x, prec, base + x_off, B.dim));
+    for (auto& g : B.groups) {
+        BufTable bufs{base + s_off, base + e_off, base + x_off, base + z_off, base + y_off};
+        TRY(run_gemm(prec, bufs, g.p1, prec, dmrgdev::GK_HEFF_Z, -1, part));
+        TRY(run_gemm(prec, bufs, g.p2, dmrgdev::P_F32, dmrgdev::GK_HEFF_Y, -1, part));
+        TRY(run_gemm(prec, bufs, g.p3, dmrgdev::P_F32, dmrgdev::GK_OTHER, -1, part));
+    }
+    DEV(dmrgdev::convert(dev_, dmrgdev::P_F32, base + y_off, dmrgdev::P_F64, y, B.dim));
+    return DMRG_OK;
 }
 
 dmrg_status Engine::energy(double* E) {

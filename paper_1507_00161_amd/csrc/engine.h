@@ -260,6 +260,7 @@ public:
                       dmrg_sweep_stats* st);
     dmrg_status layout(int32_t* bond, int64_t* dim, int32_t* nsec, int32_t* qn, int64_t* dims);
     dmrg_status apply(const double* x, double* y, int prec);
+    dmrg_status apply_static(const double* x, double* y, int prec);
     dmrg_status energy(double* E);
     dmrg_status get_psi(double* host);
     dmrg_status configs(uint64_t* out);
@@ -376,8 +377,9 @@ private:
                                const std::vector<int64_t>& roff, const std::vector<int>& rld);
     dmrg_status random_psi(Bond& B, Buf& out);
     // ev_mid >= 0: record that event between the GEMM and its split-K reduction
+    // partials: split-K partial tiles supplied by the caller (else the engine's own buffer)
     dmrg_status run_gemm(int prec, BufTable bufs, const GemmPlan& p, int cprec = -1,
-                         int kind = dmrgdev::GK_OTHER, int ev_mid = -1);
+                         int kind = dmrgdev::GK_OTHER, int ev_mid = -1, void* partials = nullptr);
     dmrg_status ensure_partials(int64_t slots);
     Buf partial_;
     dmrg_status ensure_dv(int64_t n, int kmax);
