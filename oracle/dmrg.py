@@ -217,6 +217,10 @@ class Options:
     d_min: int = 0               # DBSS: fewest block states kept (D is the most)
     n_states: int = 1            # 2: the two lowest states, truncated with their averaged density matrix
     measure: bool = False        # orbital correlations and entropies during the right-to-left half
+    # CI-DEAS start (both given, site indices): one-orbital entropies and
+    # occupations <n_i> of a preprocessing run, for the environment blocks
+    cideas_entropy: Optional[np.ndarray] = None
+    cideas_occupation: Optional[np.ndarray] = None
 
 
 @dataclasses.dataclass
@@ -260,6 +264,20 @@ class DMRG:
         self.sweeps_done = 0
         self.heff_flops = 0.0      # matmul flops of all H_eff products (timing report only)
         self.heff_seconds = 0.0
+        o = self.opts
+        self.cideas = o.cideas_entropy is not None and o.cideas_occupation is not None
+        if self.cideas:
+            self.cd_s = np.asarray(o.cideas_entropy, np.float64)[order]
+            occ = np.asarray(o.cideas_occupation, np.float64)[order]
+            # reference determinant: per species the n_species sites of largest
+            # <n_i> (ties to the lower chain position)
+            ref = 0
+            for sp_, n_sp in ((0, n_p), (1, n_n)):
+                sites = [i for i in range(n) if self.species[i] == sp_]
+                sites.sort(key=lambda i: (-occ[i], i))
+                for i in sites[:n_sp]:
+                    ref |= 1 << i
+            self.cd_ref = ref
 
     # ------------------------------------------------------------------ sectors
     def reach(self, a: int, b: int) -> set:
@@ -803,6 +821,65 @@ class DMRG:
             iso[q] = U
         return iso
 
+    def cideas_iso(self, enl: Enlarged, base: Block, D: int, lo: int):
+        """CI-DEAS environment block (the block-state paragraph cites the
+        procedure: a CI-based, dynamically extended active space grown by the
+        orbital entropy profile).  Reading: the block R = sites lo..N-1 keeps
+        determinants of its composite basis (site lo times the block R_{lo+1}
+        built before it).  Its active space is the first k of its sites in
+        decreasing one-orbital entropy (ties to the lower position); a
+        determinant belongs to the CI space of that active space when it
+        differs from the reference determinant only on those k sites.  The
+        block keeps the CI space of the largest k that holds at most D
+        determinants, then fills up to D from the next space's new members,
+        fewest differing sites first, then by the SplitMix64 key
+        (seed, 5, lo, low and high 32 bits of the determinant).  The active
+        space grows as the blocks are built from the right end toward the
+        left: the extension is dynamic."""
+        N, seed, ref = self.N, self.opts.seed, self.cd_ref
+        mask = ((1 << N) - 1) & ~((1 << lo) - 1)
+        order = sorted(range(lo, N), key=lambda i: (-self.cd_s[i], i))
+        rank = {site: k + 1 for k, site in enumerate(order)}
+        cand = []   # (level, differing sites, key, sector, row)
+        for q, parts in enl.parts.items():
+            row = 0
+            for p in parts:
+                bit = (1 << enl.site) if p.sigma else 0
+                for c0 in base.configs[p.qb]:
+                    c = c0 | bit
+                    d = (c ^ ref) & mask
+                    lev = max((rank[i] for i in range(lo, N) if (d >> i) & 1), default=0)
+                    key = hashrand.hkey(seed, 5, lo, c & 0xFFFFFFFF, c >> 32)
+                    cand.append((lev, bin(d).count("1"), key, q, row))
+                    row += 1
+        if len(cand) <= D:
+            kept = cand
+        else:
+            count = {}
+            for t in cand:
+                count[t[0]] = count.get(t[0], 0) + 1
+            kstar, cum = -1, 0
+            for k in range(0, N - lo + 1):
+                if cum + count.get(k, 0) > D:
+                    break
+                cum += count.get(k, 0)
+                kstar = k
+            kept = [t for t in cand if t[0] <= kstar]
+            nxt = sorted((t for t in cand if t[0] == kstar + 1), key=lambda t: (t[1], t[2]))
+            kept += nxt[:D - len(kept)]
+        rows = {}
+        for t in kept:
+            rows.setdefault(t[3], []).append(t[4])
+        iso = {}
+        for q in enl.dims:
+            if q not in rows:
+                continue
+            r = sorted(rows[q])
+            U = np.zeros((enl.dims[q], len(r)))
+            U[r, np.arange(len(r))] = 1.0
+            iso[q] = U
+        return iso
+
     def dbss_count(self, w_desc, D: int) -> int:
         return dbss_count(w_desc, D, self.opts.trunc_eps, self.opts.d_min)
 
@@ -981,7 +1058,10 @@ class DMRG:
             Rn = self.R[lo + 1]
             left_reach = self.reach(0, lo)
             enl, ops = self.enlarge_right(Rn, lambda q: qsub(T, q) in left_reach)
-            iso = self.selection_iso(enl.dims, D, 1, lo, mix=not self.opts.select_basis)
+            if self.cideas:
+                iso = self.cideas_iso(enl, Rn, D, lo)
+            else:
+                iso = self.selection_iso(enl.dims, D, 1, lo, mix=not self.opts.select_basis)
             self.R[lo] = self.new_block("R", lo, N, enl, ops, iso, Rn)
         self.psi = None
         self.psi2 = None

@@ -1,4 +1,4 @@
-"""Write tests/golden/oracle_energies.json from the CPU oracle alone.
+"""Write the golden files under tests/golden/ from the CPU oracle alone.
 
 Each case runs the oracle's two-site DMRG (oracle/dmrg.py) on a seeded
 workload with a fixed sweep schedule and options, and records the sweep
@@ -7,7 +7,13 @@ information and the correlations they come from).  The GPU parity tests run the 
 schedule, ordering and options and compare energies (relative 1e-8 in FP64,
 1e-6 in the mixed modes).  Nothing here touches the GPU library.
 
-    python tests/golden/make_golden.py
+    python tests/golden/make_golden.py                 all cases of CASES
+    python tests/golden/make_golden.py NAME ...        only those cases (merged into the file)
+    python tests/golden/make_golden.py --bench-schedule
+
+--bench-schedule writes oracle_bench_schedule.json: the benchmark's own
+workload (pf 8p+8n), options and D schedule (512, 512, 1024, 1024, then
+2048), one entry per sweep, the file rewritten after every sweep.
 """
 from __future__ import annotations
 
@@ -34,6 +40,8 @@ CASES = [
     # pf + g9/2 (60 sites, 12p + 12n, the 64Ge-sized space), J_z = 0 and J_z = 2
     ("pfg9_12p12n_D16", "pfg9_12p12n", None, [16, 16]),
     ("pfg9_12p12n_M2_D16", "pfg9_12p12n_M2", None, [16]),
+    ("pfg9_12p12n_D64", "pfg9_12p12n", None, [32, 64]),
+    ("pfg9_12p12n_M2_D64", "pfg9_12p12n_M2", None, [32, 64]),
     # dynamic block-state selection: the kept count follows the truncation error
     ("p_2p2n_dbss", "p_2p2n", None, [64, 64, 64], {"trunc_eps": 1e-6, "d_min": 4}),
     ("sd_4p4n_dbss", "sd_4p4n", None, [128, 128, 128], {"trunc_eps": 1e-3, "d_min": 8}),
@@ -57,9 +65,44 @@ def hamiltonian(spec):
     return make_hamiltonian(make_space(space), seed, n_p, n_n, two_M)
 
 
+# the benchmark's schedule and options (bench.py: the D ramp, then D = 2048)
+BENCH_OPTS = dict(davidson_tol=1e-7, noise=1e-4, noise_sweeps=2, seed=1507)
+BENCH_SCHEDULE = [512, 512, 1024, 1024, 2048, 2048, 2048]
+
+
+def bench_schedule():
+    h = WORKLOADS["pf_8p8n"].hamiltonian()
+    sp = h.space
+    o = dmrg.DMRG(h.eps, h.V, sp.species, sp.two_m, h.n_p, h.n_n, h.two_M, None, dmrg.Options(**BENCH_OPTS))
+    out = {"workload": "pf_8p8n", "options": BENCH_OPTS, "D": [], "energies": [], "kept_max": [],
+           "products": [], "seconds": []}
+    path = os.path.join(HERE, "oracle_bench_schedule.json")
+    for D in BENCH_SCHEDULE:
+        t = time.time()
+        r = o.sweep(D)
+        out["D"].append(D)
+        out["energies"].append(r["energy"])
+        out["kept_max"].append(r["kept_max"])
+        out["products"].append(r["nprod"])
+        out["seconds"].append(time.time() - t)
+        with open(path, "w") as f:
+            json.dump(out, f, indent=1)
+        print(f"bench schedule D={D}: {r['energy']} ({time.time() - t:.0f} s)", flush=True)
+
+
 def main():
+    if sys.argv[1:] == ["--bench-schedule"]:
+        bench_schedule()
+        return
+    only = set(sys.argv[1:])
+    path = os.path.join(HERE, "oracle_energies.json")
     out = {"options": OPTS, "cases": {}}
+    if only:
+        with open(path) as f:
+            out = json.load(f)
     for name, spec, oseed, sched, *extra in CASES:
+        if only and name not in only:
+            continue
         extra = extra[0] if extra else {}
         h = hamiltonian(spec)
         sp = h.space
@@ -83,7 +126,7 @@ def main():
                                                    h.n_p, h.n_n, h.two_M)[0])
         out["cases"][name] = case
         print(f"{name}: {energies} ({time.time() - t:.1f} s)", flush=True)
-    with open(os.path.join(HERE, "oracle_energies.json"), "w") as f:
+    with open(path, "w") as f:
         json.dump(out, f, indent=1)
 
 

@@ -315,3 +315,116 @@ def test_heff_diag_equals_assembled_diagonal(name, n_p, n_n, two_M, D):
     o.sweep(D, on_step=hook)
     o.sweep(D, on_step=hook)
     assert nchk[0] == 4 * (space.n_sites - 1)
+
+
+# ------------------------------------------------------------------ CI-DEAS
+def _profile(h):
+    """One-orbital entropies and occupations of the exact ground state."""
+    sp_ = h.space
+    _, basis, vec = ed.ground_state(h.eps, h.V, sp_.species, sp_.two_m, h.n_p, h.n_n, h.two_M)
+    from oracle import entropy
+    n, _, _ = entropy.correlations_from_vector(basis, vec, sp_.n_sites)
+    s1, _ = entropy.entropies_of_vector(basis, vec, sp_.n_sites)
+    return s1, n
+
+
+@pytest.mark.parametrize("oseed", [None, 6])
+def test_cideas_exact_at_full_rank(oseed):
+    h = WORKLOADS["p_2p2n"].hamiltonian()
+    sp_ = h.space
+    s1, n1 = _profile(h)
+    e0 = ed.ground_energy(h.eps, h.V, sp_.species, sp_.two_m, 2, 2, 0)[0]
+    order = None if oseed is None else random_ordering(12, oseed)
+    o = dmrg.DMRG(h.eps, h.V, sp_.species, sp_.two_m, 2, 2, 0, order,
+                  dmrg.Options(davidson_tol=1e-11, seed=3, cideas_entropy=s1, cideas_occupation=n1))
+    assert o.cideas
+    r = [o.sweep(64) for _ in range(2)]
+    assert abs(r[-1]["energy"] - e0) < 1e-10
+
+
+def test_cideas_variational_truncated():
+    space = make_space("sd")
+    h = make_hamiltonian(space, 21, 2, 2, 0)
+    s1, n1 = _profile(h)
+    e0 = ed.ground_energy(h.eps, h.V, space.species, space.two_m, 2, 2, 0)[0]
+    o = dmrg.DMRG(h.eps, h.V, space.species, space.two_m, 2, 2, 0, None,
+                  dmrg.Options(davidson_tol=1e-9, noise=1e-4, noise_sweeps=1, seed=3,
+                               cideas_entropy=s1, cideas_occupation=n1))
+    res = [o.sweep(8)["energy"] for _ in range(3)]
+    assert all(rec.theta >= e0 - 1e-10 for rec in o.records)
+    assert res[2] <= res[0] + 1e-9
+
+
+def _popcount(x):
+    return bin(x).count("1")
+
+
+@pytest.mark.parametrize("name,n_p,n_n,two_M,D,oseed", [("p", 2, 2, 0, 6, 1), ("sd", 2, 3, 1, 9, 2),
+                                                     ("sd", 4, 4, 0, 30, None)])
+def test_cideas_blocks_against_definition(name, n_p, n_n, two_M, D, oseed):
+    """Every environment block of the CI-DEAS start, against the rule stated
+    with the nested CI spaces C_k (determinants differing from the reference
+    only on the k most entropic sites of the block): the block holds all of
+    C_k* for the largest k* with |C_k*| <= D, and is completed to D states
+    from C_{k*+1} with the fewest differing sites first.  The candidate
+    determinants are built independently: each determinant of the block
+    before it, with the new site empty or occupied, kept when the sites to
+    its left can complete the target."""
+    space = make_space(name)
+    h = make_hamiltonian(space, 44, n_p, n_n, two_M)
+    rng = np.random.default_rng(9)
+    s1 = rng.uniform(0.0, 0.69, space.n_sites)
+    n1 = rng.uniform(0.0, 1.0, space.n_sites)
+    order = None if oseed is None else random_ordering(space.n_sites, oseed)
+    o = dmrg.DMRG(h.eps, h.V, space.species, space.two_m, n_p, n_n, two_M, order,
+                  dmrg.Options(seed=5, cideas_entropy=s1, cideas_occupation=n1))
+    o.initialize(D)
+    N, T = o.N, o.T
+    # reference and entropy in chain positions, from the inputs directly
+    sc = np.asarray(s1)[o.order]
+    oc = np.asarray(n1)[o.order]
+    ref = 0
+    for sp_, cnt in ((0, n_p), (1, n_n)):
+        sites = sorted((i for i in range(N) if o.species[i] == sp_), key=lambda i: (-oc[i], i))
+        for i in sites[:cnt]:
+            ref |= 1 << i
+    truncated = 0
+    for lo in range(N - 1, 1, -1):
+        prev, blk = o.R[lo + 1], o.R[lo]
+        reach = o.reach(0, lo)
+
+        def qn(c):
+            q = [0, 0, 0]
+            for i in range(N):
+                if (c >> i) & 1:
+                    q[0 if o.species[i] == 0 else 1] += 1
+                    q[2] += int(o.two_m[i])
+            return tuple(q)
+
+        cands = [c0 | (b << lo) for cs in prev.configs.values() for c0 in cs for b in (0, 1)]
+        cands = [c for c in cands if dmrg.qsub(T, qn(c)) in reach]
+        kept = sorted(c for cs in blk.configs.values() for c in cs)
+        assert len(kept) == min(D, len(cands)) and len(set(kept)) == len(kept)
+        if len(cands) <= D:
+            assert kept == sorted(cands)
+            continue
+        truncated += 1
+        top = sorted(range(lo, N), key=lambda i: (-sc[i], i))
+        diff = {c: (c ^ ref) & ~((1 << lo) - 1) for c in cands}
+
+        def space_k(k):
+            allowed = 0
+            for i in top[:k]:
+                allowed |= 1 << i
+            return {c for c in cands if diff[c] & ~allowed == 0}
+
+        k = 0
+        while len(space_k(k + 1)) <= D:
+            k += 1
+        inner, outer = space_k(k), space_k(k + 1)
+        ks = set(kept)
+        assert inner <= ks <= outer
+        extra, rest = ks - inner, outer - ks
+        if extra and rest:
+            assert max(_popcount(diff[c]) for c in extra) <= min(_popcount(diff[c]) for c in rest)
+    assert truncated > 0
