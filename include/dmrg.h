@@ -82,6 +82,14 @@ typedef struct dmrg_options {
      * i <= b <n_i>, <n_i n_j> and <c+_i c_j>, with j = b + 1.  Left blocks then
      * carry the occupation operator of each of their sites.  0 (default): off. */
     int32_t measure;
+    /* 1: each bond's H_eff product (input and output conversions, the GEMM
+     * phases, their split-K reductions) is captured once in a HIP graph and
+     * the graph is replayed for every product at that bond (input and output
+     * pass through fixed staging vectors).  Products then run as one graph
+     * launch; the per-phase GEMM statistics are not collected.  Products that
+     * need several term groups, and products advanced by dmrg_sweep_many, are
+     * launched directly.  0 (default): direct launches. */
+    int32_t graph;
 } dmrg_options;
 
 typedef struct dmrg_sweep_stats {
@@ -191,6 +199,27 @@ dmrg_status dmrg_heff_layout(dmrg_ctx* ctx, int32_t* bond, int64_t* dim, int32_t
  * DMRG_ERR_STATE before the first sweep step. */
 dmrg_status dmrg_heff_apply(dmrg_ctx* ctx, const double* psi_in, double* psi_out, int32_t precision);
 
+/* CI-DEAS start (the block-state paragraph: the environmental error of the
+ * first sweeps is reduced by a CI-based, dynamically extended active space
+ * grown by the orbital entropy profile).  s1[n_sites] and n1[n_sites] (host,
+ * site indices, copied) are the one-orbital entropies and occupations <n_i>
+ * of a preprocessing run (dmrg_orbital_entropies of a measuring sweep).  The
+ * next sweep re-initialises: every environment block R = chain positions
+ * lo..N-1 keeps determinants of its composite basis (position lo times the
+ * block built before it): those that differ from the reference determinant
+ * (per species the sites of largest <n_i>, ties to the lower position) only
+ * on the block's k most entropic positions, for the largest k whose CI space
+ * holds at most D of them, completed to D from the next space with the
+ * fewest differing positions first, then the SplitMix64 key
+ * (seed, 5, lo, low and high 32 bits of the determinant as a chain-position
+ * mask).  The first state is the hash-random vector.  Both NULL: back to the
+ * hash start (also re-initialising).  Reloading the Hamiltonian clears it.
+ * Errors: STATE before dmrg_load_hamiltonian; ARG for one NULL array, or
+ * values not finite, entropies below 0 or occupations outside [0, 1] (by
+ * more than 1e-9: measured values carry rounding, and only their order
+ * matters). */
+dmrg_status dmrg_set_cideas(dmrg_ctx* ctx, const double* s1, const double* n1);
+
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the same
  * product as dmrg_heff_apply (same plans, kernels and launch order, so the
@@ -230,12 +259,20 @@ dmrg_status dmrg_get_psi(dmrg_ctx* ctx, double* psi_host);
 dmrg_status dmrg_heff_configs(dmrg_ctx* ctx, uint64_t* configs);
 
 /* Advance n distinct contexts by one sweep each with their own ordering
- * (orderings[i] may be NULL) and D[i].  The sweeps are driven from up to 8
- * host threads, one context per thread at a time; each context keeps its own
- * stream, so small solves overlap on the device and every result equals that
- * of a separate dmrg_sweep.  Per-context status in out[i].status (out may be
- * NULL); returns the first error in context order, else the largest warning.
- * A NULL or repeated context -> DMRG_ERR_ARG before any work. */
+ * (orderings[i] may be NULL) and D[i] (independent solves, e.g. many small
+ * Hamiltonians).  Each context is driven by a host thread of its own (at most
+ * 256 threads; further contexts wait for a free one).  When all contexts are
+ * on one device their H_eff products are launched together by one launcher
+ * thread: the products pending when it takes them (those that arrived while
+ * the previous group was launched) form one grouped launch of the persistent
+ * GEMM per product phase over all their plans, and one grouped split-K
+ * reduction, on a stream of the call; each context's own work stays on its
+ * stream, ordered around those launches by events.  Every result equals that of a separate
+ * dmrg_sweep (same plans and arithmetic).  Bonds whose product needs several
+ * term groups (larger than the scratch limit) are launched by their context.
+ * Per-context status in out[i].status (out may be NULL); returns the first
+ * error in context order, else the largest warning.  A NULL or repeated
+ * context -> DMRG_ERR_ARG before any work. */
 dmrg_status dmrg_sweep_many(dmrg_ctx** ctxs, int32_t n, const int32_t* const* orderings,
                             const int32_t* D, dmrg_sweep_stats* out);
 

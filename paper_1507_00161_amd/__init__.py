@@ -32,7 +32,7 @@ class Options(ctypes.Structure):
                 ("stream", ctypes.c_void_p), ("mem_cap_bytes", ctypes.c_uint64),
                 ("scratch_bytes", ctypes.c_uint64), ("trunc_eps", ctypes.c_double),
                 ("d_min", ctypes.c_int32), ("n_states", ctypes.c_int32),
-                ("measure", ctypes.c_int32)]
+                ("measure", ctypes.c_int32), ("graph", ctypes.c_int32)]
 
 
 class SweepStats(ctypes.Structure):
@@ -79,6 +79,7 @@ def declare(lib: ctypes.CDLL) -> ctypes.CDLL:
         "dmrg_heff_layout": (I32, [P, ctypes.POINTER(I32), ctypes.POINTER(I64), ctypes.POINTER(I32), P, P]),
         "dmrg_heff_apply": (I32, [P, P, P, I32]),
         "dmrg_check_fp64": (I32, [P, I32]),
+        "dmrg_set_cideas": (I32, [P, P, P]),
         "dmrg_heff_apply_noalloc": (I32, [P, P, P, I32]),
         "dmrg_energy": (I32, [P, ctypes.POINTER(D)]),
         "dmrg_get_psi": (I32, [P, P]),
@@ -223,6 +224,17 @@ class Context:
         """y = H_eff x with the library's fixed device scratch (dmrg_heff_apply_noalloc)."""
         self._check(self._lib.dmrg_heff_apply_noalloc(self._h, ctypes.c_void_p(_dev_ptr(x)),
                                                       ctypes.c_void_p(_dev_ptr(y)), precision))
+
+    def set_cideas(self, s1=None, n1=None) -> None:
+        """CI-DEAS start from entropies and occupations (site indices) of a
+        preprocessing run; both None: the hash start (dmrg_set_cideas)."""
+        if s1 is None and n1 is None:
+            self._check(self._lib.dmrg_set_cideas(self._h, None, None))
+            return
+        a, b = _f64(s1), _f64(n1)
+        if a.size != self.n_sites or b.size != self.n_sites:
+            raise ValueError("s1 and n1 need n_sites entries")
+        self._check(self._lib.dmrg_set_cideas(self._h, _ptr(a), _ptr(b)))
 
     def check_fp64(self, on: bool) -> None:
         """Repeat every mixed-precision solve in FP64 from the same guess and

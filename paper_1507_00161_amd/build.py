@@ -38,7 +38,7 @@ def build(verbose: bool = False) -> str:
     dev_obj = os.path.join(objdir, "device.o")
     _run([hipcc, *HIP_FLAGS, "-c", os.path.join(CSRC, "device.hip"), "-o", dev_obj])
     objs.append(dev_obj)
-    for src in ("engine.cpp", "capi.cpp", "entropy.cpp"):
+    for src in ("engine.cpp", "capi.cpp", "entropy.cpp", "batch.cpp"):
         obj = os.path.join(objdir, src.replace(".cpp", ".o"))
         _run(["g++", *HOST_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj])
         objs.append(obj)

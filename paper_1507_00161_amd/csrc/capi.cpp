@@ -6,10 +6,12 @@
 #include <exception>
 #include <new>
 #include <string>
+#include <memory>
 #include <thread>
 #include <vector>
 
 #include "../../include/dmrg.h"
+#include "batch.h"
 #include "device.h"
 #include "engine.h"
 
@@ -63,6 +65,7 @@ void dmrg_default_options(dmrg_options* o) {
     o->d_min = 0;
     o->n_states = 1;
     o->measure = 0;
+    o->graph = 0;
 }
 
 dmrg_status dmrg_create(const dmrg_options* opt, dmrg_ctx** out) {
@@ -74,7 +77,7 @@ dmrg_status dmrg_create(const dmrg_options* opt, dmrg_ctx** out) {
     if (o.precision < 0 || o.precision > 2 || o.davidson_tol <= 0 || o.davidson_max_iter < 1 ||
         o.davidson_max_subspace < 2 || o.davidson_max_subspace > 32 || o.noise < 0 || o.tie_tol < 0 ||
         !(o.trunc_eps >= 0) || o.d_min < 0 || o.n_states < 1 || o.n_states > 2 ||
-        (o.measure != 0 && o.measure != 1)) {
+        (o.measure != 0 && o.measure != 1) || (o.graph != 0 && o.graph != 1)) {
         g_create_err = "invalid option value";
         return DMRG_ERR_ARG;
     }
@@ -131,6 +134,10 @@ dmrg_status dmrg_heff_apply_noalloc(dmrg_ctx* c, const double* x, double* y, int
     return guarded(c, [&] { return c->eng->apply_static(x, y, precision); });
 }
 
+dmrg_status dmrg_set_cideas(dmrg_ctx* c, const double* s1, const double* n1) {
+    return guarded(c, [&] { return c->eng->set_cideas(s1, n1); });
+}
+
 dmrg_status dmrg_check_fp64(dmrg_ctx* c, int32_t on) {
     if (!c) return DMRG_ERR_ARG;
     if (on != 0 && on != 1) {
@@ -174,13 +181,25 @@ dmrg_status dmrg_sweep_many(dmrg_ctx** ctxs, int32_t n, const int32_t* const* or
         for (int32_t j = 0; j < i; ++j)
             if (ctxs[j] == ctxs[i]) return DMRG_ERR_ARG;   // a context runs on one thread at a time
     }
-    // Each context has its own stream, so sweeps driven from several host
-    // threads overlap on the device: small solves that cannot fill the GPU
-    // alone run side by side.  Every context's work stays in its own order,
-    // so results equal one-at-a-time sweeps.
+    // Every context is driven by a host thread of its own (at most 256 at a
+    // time).  When all of them run on one device their H_eff products go
+    // through one batch: products pending together are launched as one
+    // grouped GEMM per phase over all their plans.  Each context's work keeps
+    // its own order, so the results equal one-at-a-time sweeps.
     std::vector<dmrg_status> st(n, DMRG_OK);
     std::vector<dmrg_sweep_stats> res(n);
     std::atomic<int32_t> next(0);
+    const int nt = (int)std::min<int32_t>(n, 256);
+    std::unique_ptr<dm::Batch> batch;
+    bool same = n > 1;
+    for (int32_t i = 1; i < n && same; ++i)
+        same = dmrgdev::ctx_device(ctxs[i]->dev) == dmrgdev::ctx_device(ctxs[0]->dev);
+    if (same) {
+        batch.reset(new dm::Batch(dmrgdev::ctx_device(ctxs[0]->dev)));
+        if (!batch->ok()) batch.reset();   // independent sweeps
+    }
+    if (batch)
+        for (int32_t i = 0; i < n; ++i) ctxs[i]->eng->attach_batch(batch.get());
     auto worker = [&] {
         for (int32_t i = next++; i < n; i = next++) {
             dmrgdev::bind(ctxs[i]->dev);
@@ -190,11 +209,12 @@ dmrg_status dmrg_sweep_many(dmrg_ctx** ctxs, int32_t n, const int32_t* const* or
             res[i] = s;
         }
     };
-    const int nt = (int)std::min<int32_t>(n, 8);
     std::vector<std::thread> pool;
     for (int t = 1; t < nt; ++t) pool.emplace_back(worker);
     worker();
     for (auto& t : pool) t.join();
+    if (batch)
+        for (int32_t i = 0; i < n; ++i) ctxs[i]->eng->attach_batch(nullptr);
     dmrg_status worst = DMRG_OK;
     for (int32_t i = 0; i < n; ++i) {
         if (out) out[i] = res[i];

@@ -94,6 +94,43 @@ int gemm(Ctx* c, int ab_prec, int c_prec, void* const* bufs, const GemmTask* d_t
          const GemmChunk* d_chunks, int kind = GK_OTHER);
 int gemm_reduce(Ctx* c, int c_prec, void* const* bufs, const RedTask* d_tasks, int ntasks);
 
+// Grouped launch of several plans (independent solves advanced together):
+// one descriptor per plan with its buffer table, task and chunk lists and
+// schedule; work-group g runs plan p for prefix[p] <= g < prefix[p + 1] as
+// that plan's work-group g - prefix[p].  d_plans and d_prefix (nplans + 1
+// entries, prefix[nplans] = total_wg) are device arrays.
+struct PlanDesc {
+    void* bufs[kMaxBufs];
+    const GemmTask* tasks;
+    const GemmChunk* chunks;
+    Sched sc;
+};
+int gemm_multi(Ctx* c, int ab_prec, int c_prec, const PlanDesc* d_plans, const int32_t* d_prefix, int nplans,
+               int total_wg, int kind);
+// split-K reductions of several plans: reduction x of plan p is block
+// prefix[p] + x (prefix[nplans] = total)
+struct RedDesc {
+    void* bufs[kMaxBufs];
+    const RedTask* reds;
+};
+int gemm_reduce_multi(Ctx* c, int c_prec, const RedDesc* d_plans, const int32_t* d_prefix, int nplans, int total);
+
+// Cross-stream ordering (opaque event handles, no timing)
+void* xevent_create(Ctx* c);             // nullptr on failure
+void xevent_destroy(void* e);
+int xevent_record(Ctx* c, void* e);      // record on c's stream
+int xevent_wait(Ctx* c, void* e);        // c's stream waits for the last record of e
+int xevent_sync(Ctx* c, void* e);        // the host waits for the last record of e
+int ctx_device(Ctx* c);
+
+// HIP graphs: capture the work queued on the context stream between begin and
+// end (nothing runs meanwhile) into an executable graph; launch it on the
+// stream as often as needed; destroy it when its buffers change.
+int graph_begin(Ctx* c);
+int graph_end(Ctx* c, void** exec);
+int graph_launch(Ctx* c, void* exec);
+void graph_destroy(void* exec);
+
 // ------------------------------------------------------- linear combination
 // dst[r0+r, c0+c] = sum_terms coef * src(r0+r, c0+c) with src(r, c) =
 // S[r*ld + c], S[c*ld + r] (trans) or delta_rc (ident).  FP64.

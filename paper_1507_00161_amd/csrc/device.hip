@@ -15,6 +15,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstddef>
 #include <cstring>
 #include <mutex>
 #include <string>
@@ -224,6 +225,54 @@ int bind(Ctx* c) {
     HIPCHK(c, hipSetDevice(c->device));
     return 0;
 }
+void* xevent_create(Ctx* c) {
+    hipEvent_t e = nullptr;
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+        c->err = "hipEventCreate failed";
+        return nullptr;
+    }
+    return (void*)e;
+}
+void xevent_destroy(void* e) {
+    if (e) hipEventDestroy((hipEvent_t)e);
+}
+int xevent_sync(Ctx* c, void* e) {
+    HIPCHK(c, hipEventSynchronize((hipEvent_t)e));
+    return 0;
+}
+int xevent_record(Ctx* c, void* e) {
+    HIPCHK(c, hipEventRecord((hipEvent_t)e, c->stream));
+    return 0;
+}
+int xevent_wait(Ctx* c, void* e) {
+    HIPCHK(c, hipStreamWaitEvent(c->stream, (hipEvent_t)e, 0));
+    return 0;
+}
+int ctx_device(Ctx* c) { return c->device; }
+
+int graph_begin(Ctx* c) {
+    HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+    return 0;
+}
+int graph_end(Ctx* c, void** exec) {
+    *exec = nullptr;
+    hipGraph_t g = nullptr;
+    HIPCHK(c, hipStreamEndCapture(c->stream, &g));
+    hipGraphExec_t x = nullptr;
+    hipError_t e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    if (e != hipSuccess) return seterr(c, "hipGraphInstantiate", e);
+    *exec = (void*)x;
+    return 0;
+}
+int graph_launch(Ctx* c, void* exec) {
+    HIPCHK(c, hipGraphLaunch((hipGraphExec_t)exec, c->stream));
+    return 0;
+}
+void graph_destroy(void* exec) {
+    if (exec) hipGraphExecDestroy((hipGraphExec_t)exec);
+}
+
 int event_record(Ctx* c, int slot) {
     HIPCHK(c, hipEventRecord(c->ev[slot], c->stream));
     return 0;
@@ -392,16 +441,53 @@ struct Slice {
 #pragma unroll
         for (int u = 0; u < E; ++u) v[u] = bload<T>(rs, u < nv ? base + u * step : kOutside, 0);
     }
+    // LDS position of slice column k: FP32 / FP64 slices are stored k-permuted,
+    // k -> E (k % 4) + k / 4, so that the values a lane feeds to its MFMA steps
+    // q = 0 .. E-1 (k = 4 q + lane / 16) are contiguous and read as 16-byte
+    // vectors; BF16 keeps k in order (its fragments are already 8 wide).
+    static __device__ __forceinline__ int pos(int k) { return sizeof(T) == 2 ? k : E * (k & 3) + (k >> 2); }
     __device__ __forceinline__ void store_k(T* __restrict__ Sm, int tid) const {
         constexpr int RS = NTH / BK;
         const int k = tid % BK, r = tid / BK;
+        const int pk = pos(k);
 #pragma unroll
-        for (int u = 0; u < E; ++u) Sm[(r + RS * u) * LDK + k] = scaled(v[u], scale);
+        for (int u = 0; u < E; ++u) Sm[(r + RS * u) * LDK + pk] = scaled(v[u], scale);
     }
     __device__ __forceinline__ void store_m(T* __restrict__ Sm, int tid) const {
         const int r = (tid & 15) + 16 * (tid >> 6), k = (tid >> 4) & 3;
+        if constexpr (sizeof(T) == 2) {
 #pragma unroll
-        for (int u = 0; u < E; ++u) Sm[r * LDK + k + 4 * u] = scaled(v[u], scale);
+            for (int u = 0; u < E; ++u) Sm[r * LDK + k + 4 * u] = scaled(v[u], scale);
+        } else {
+            // elements (r, k + 4 u), u = 0 .. E-1, land at E k + u: contiguous
+            typedef T v4 __attribute__((ext_vector_type(16 / sizeof(T))));
+            constexpr int W = 16 / sizeof(T);
+            T* dst = &Sm[r * LDK + E * k];
+#pragma unroll
+            for (int h = 0; h < E / W; ++h) {
+                v4 x;
+#pragma unroll
+                for (int w = 0; w < W; ++w) x[w] = scaled(v[h * W + w], scale);
+                *(v4*)(dst + h * W) = x;
+            }
+        }
+    }
+};
+
+// Where a GEMM finds its buffer table: a kernel argument (single plan), or
+// an LDS copy of a plan's table (grouped launches); in both cases a buffer's
+// base address is uniform over the work-group and kept in scalar registers.
+struct ArgBufs {
+    const Bufs& b;
+    __device__ __forceinline__ void* get(int i) const { return b.p[i]; }
+};
+struct LdsBufs {
+    const Bufs* b;   // in LDS
+    __device__ __forceinline__ void* get(int i) const {
+        const uint64_t v = (uint64_t)b->p[i];
+        const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+        const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+        return (void*)(((uint64_t)hi << 32) | lo);
     }
 };
 
@@ -411,14 +497,34 @@ struct Slice {
 // (possibly of the next task) are in flight while the MFMAs consume the current
 // slice from LDS; a task's epilogue is written when its last slice has been
 // consumed.
-template <class T, class TC, int BK>
-__device__ __forceinline__ void gemm_body(const Bufs& bufs, const GemmTask* __restrict__ tasks,
-                                          const GemmChunk* __restrict__ chunks, const Sched& sc) {
+// Task, chunk and schedule lists are read-only during a launch: they are read
+// through constant-address-space pointers, so that their uniform loads are
+// scalar loads whatever the origin of the pointers (kernel arguments, or a
+// plan table in memory for grouped launches).
+template <class T> using cptr = const __attribute__((address_space(4))) T*;
+template <class T> __device__ __forceinline__ cptr<T> as_const(const T* p) { return (cptr<T>)(uintptr_t)p; }
+// element i of a constant-address-space array, copied word by word
+template <class T> __device__ __forceinline__ T ldc(cptr<T> p, int64_t i) {
+    static_assert(sizeof(T) % 4 == 0, "descriptor size");
+    const __attribute__((address_space(4))) uint32_t* w = (const __attribute__((address_space(4))) uint32_t*)(p + i);
+    T v;
+    uint32_t* o = reinterpret_cast<uint32_t*>(&v);
+#pragma unroll
+    for (int k = 0; k < (int)(sizeof(T) / 4); ++k) o[k] = w[k];
+    return v;
+}
+
+template <class T, class TC, int BK, class BS>
+__device__ __forceinline__ void gemm_body(const BS bufs, const GemmTask* __restrict__ tasks_g,
+                                          const GemmChunk* __restrict__ chunks_g, const Sched& sc, int wg, int nwg) {
+    const cptr<GemmTask> tasks = as_const(tasks_g);
+    const cptr<GemmChunk> chunks = as_const(chunks_g);
+    const cptr<int32_t> wg_off = as_const(sc.wg_off);
     typedef typename MmaTraits<T>::acc_t acc_t;
     typedef Slice<T, BK> SL;
     constexpr int LDK = SL::LDK;
-    __shared__ T As[2][TM * LDK];
-    __shared__ T Bs[2][TN * LDK];
+    __shared__ __attribute__((aligned(16))) T As[2][TM * LDK];
+    __shared__ __attribute__((aligned(16))) T Bs[2][TN * LDK];
     const int tid = threadIdx.x;
     // The wave index is uniform across a wave.  The FP32 and BF16 bodies keep
     // it in a scalar register: the quadrant tests below become scalar branches
@@ -430,8 +536,8 @@ __device__ __forceinline__ void gemm_body(const Bufs& bufs, const GemmTask* __re
     const int lane = tid & 63;
     const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;   // wave quadrant
     const int fr = lane & 15, fk = lane >> 4;
-    int ti = sc.wg_off[blockIdx.x];
-    const int hi = sc.wg_off[blockIdx.x + 1];
+    int ti = wg_off[wg];
+    const int hi = wg_off[wg + 1];
     acc_t acc[2][2];
 #pragma unroll
     for (int a = 0; a < 2; ++a)
@@ -439,8 +545,8 @@ __device__ __forceinline__ void gemm_body(const Bufs& bufs, const GemmTask* __re
         for (int b = 0; b < 2; ++b) acc[a][b] = acc_t{0, 0, 0, 0};
     SL ra, rb;
     auto load = [&](const GemmTask& t, const GemmChunk& ch, int k0) {
-        const T* A = (const T*)bufs.p[ch.a_buf] + ch.a_off;
-        const T* B = (const T*)bufs.p[ch.b_buf] + ch.b_off;
+        const T* A = (const T*)bufs.get(ch.a_buf) + ch.a_off;
+        const T* B = (const T*)bufs.get(ch.b_buf) + ch.b_off;
         typedef typename MmaTraits<T>::scale_t S;
         const S alpha = (S)ch.alpha;
         ra.load(A, !ch.a_trans, ch.lda, t.m0, t.mt, k0, ch.K, alpha, tid);
@@ -453,7 +559,7 @@ __device__ __forceinline__ void gemm_body(const Bufs& bufs, const GemmTask* __re
         else rb.store_k(Bs[buf], tid);
     };
     auto epilogue = [&](const GemmTask& t) {
-        TC* C = (TC*)bufs.p[t.c_buf] + t.c_off;
+        TC* C = (TC*)bufs.get(t.c_buf) + t.c_off;
         const int64_t ldc = t.c_local ? TN : t.ldc;
         const int64_t base = t.c_local ? 0 : (int64_t)t.m0 * t.ldc + t.n0;
         TC old[2][2][4];
@@ -487,17 +593,17 @@ __device__ __forceinline__ void gemm_body(const Bufs& bufs, const GemmTask* __re
                 }
     };
     if (ti < hi) {
-        GemmTask tk = tasks[ti];
+        GemmTask tk = ldc(tasks, ti);
         int c = tk.chunk_begin;
-        GemmChunk ch = chunks[c];
+        GemmChunk ch = ldc(chunks, c);
         int k0 = 0;
         // descriptors of this work-group's next task, fetched a whole task ahead
         int pti = ti + 1;
         GemmTask ptk = tk;
         GemmChunk pch = ch;
         if (pti < hi) {
-            ptk = tasks[pti];
-            pch = chunks[ptk.chunk_begin];
+            ptk = ldc(tasks, pti);
+            pch = ldc(chunks, ptk.chunk_begin);
         }
         load(tk, ch, 0);
         store(ch, 0);
@@ -513,7 +619,7 @@ __device__ __forceinline__ void gemm_body(const Bufs& bufs, const GemmTask* __re
                 nk0 = 0;
                 nc = c + 1;
                 if (nc < tk.chunk_end) {
-                    nch = chunks[nc];
+                    nch = ldc(chunks, nc);
                 } else {
                     newtask = true;
                     more = pti < hi;
@@ -533,8 +639,10 @@ __device__ __forceinline__ void gemm_body(const Bufs& bufs, const GemmTask* __re
                 if constexpr (sizeof(T) == 2) return *(const F*)&S[row * LDK + s * KS + 8 * fk];
                 else return S[row * LDK + s * KS + fk];
             };
-            // FP64 / FP32: all fragments of the slice first, then the MFMAs back to
-            // back; BF16 (8 VGPRs of fragments per step): one step at a time
+            // FP64 / FP32: all fragments of the slice first (k-permuted rows: a
+            // lane's NS values are contiguous, read as 16-byte vectors), then the
+            // MFMAs back to back; BF16 (8 VGPRs of fragments per step): one step
+            // at a time
             constexpr int NF = sizeof(T) == 2 ? 1 : NS;
             F av[NF][2], bv[NF][2];
             auto fetch = [&](int q) {
@@ -543,9 +651,27 @@ __device__ __forceinline__ void gemm_body(const Bufs& bufs, const GemmTask* __re
 #pragma unroll
                 for (int b = 0; b < 2; ++b) bv[q % NF][b] = frag(Bb, wn + b * 16 + fr, q);
             };
-            if (NF == NS) {
+            if constexpr (NF == NS && sizeof(T) == 2) {
 #pragma unroll
                 for (int q = 0; q < NS; ++q) fetch(q);
+            } else if constexpr (NF == NS) {
+                typedef T v4 __attribute__((ext_vector_type(16 / sizeof(T))));
+                constexpr int W = 16 / sizeof(T);
+#pragma unroll
+                for (int a = 0; a < 2; ++a) {
+                    const T* pa = &Ab[(wm + a * 16 + fr) * LDK + NS * fk];
+                    const T* pb = &Bb[(wn + a * 16 + fr) * LDK + NS * fk];
+#pragma unroll
+                    for (int h = 0; h < NS / W; ++h) {
+                        const v4 xa = *(const v4*)(pa + h * W);
+                        const v4 xb = *(const v4*)(pb + h * W);
+#pragma unroll
+                        for (int w = 0; w < W; ++w) {
+                            av[h * W + w][a] = xa[w];
+                            bv[h * W + w][a] = xb[w];
+                        }
+                    }
+                }
             }
             // MFMAs of 16 x 16 blocks that lie wholly outside the tile, and
             // K steps past the chunk's end, are skipped (wave-uniform tests):
@@ -581,8 +707,8 @@ __device__ __forceinline__ void gemm_body(const Bufs& bufs, const GemmTask* __re
                     ti = pti;
                     pti = ti + 1;
                     if (pti < hi) {
-                        ptk = tasks[pti];
-                        pch = chunks[ptk.chunk_begin];
+                        ptk = ldc(tasks, pti);
+                        pch = ldc(chunks, ptk.chunk_begin);
                     }
                 }
             }
@@ -597,10 +723,10 @@ __device__ __forceinline__ void gemm_body(const Bufs& bufs, const GemmTask* __re
         }
     }
     // tasks without chunks: clear their tile (beta = 0) or leave it (beta = 1)
-    for (int t = sc.nfull + blockIdx.x; t < sc.ntasks; t += gridDim.x) {
-        const GemmTask z = tasks[t];
+    for (int t = sc.nfull + wg; t < sc.ntasks; t += nwg) {
+        const GemmTask z = ldc(tasks, t);
         if (z.beta) continue;
-        TC* C = (TC*)bufs.p[z.c_buf] + z.c_off;
+        TC* C = (TC*)bufs.get(z.c_buf) + z.c_off;
         const int64_t ldc = z.c_local ? TN : z.ldc;
         const int64_t base = z.c_local ? 0 : (int64_t)z.m0 * z.ldc + z.n0;
         for (int e = tid; e < TM * TN; e += NTH) {
@@ -614,15 +740,88 @@ __device__ __forceinline__ void gemm_body(const Bufs& bufs, const GemmTask* __re
 // H_eff phases from the renormalisation and prediction GEMMs.
 template <class T, class TC, int BK>
 __global__ void __launch_bounds__(NTH, 4) k_gemm(Bufs b, const GemmTask* t, const GemmChunk* c, Sched s) {
-    gemm_body<T, TC, BK>(b, t, c, s);
+    gemm_body<T, TC, BK>(ArgBufs{b}, t, c, s, blockIdx.x, gridDim.x);
 }
 template <class T, class TC, int BK>
 __global__ void __launch_bounds__(NTH, 4) k_heff_z(Bufs b, const GemmTask* t, const GemmChunk* c, Sched s) {
-    gemm_body<T, TC, BK>(b, t, c, s);
+    gemm_body<T, TC, BK>(ArgBufs{b}, t, c, s, blockIdx.x, gridDim.x);
 }
 template <class T, class TC, int BK>
 __global__ void __launch_bounds__(NTH, 4) k_heff_y(Bufs b, const GemmTask* t, const GemmChunk* c, Sched s) {
-    gemm_body<T, TC, BK>(b, t, c, s);
+    gemm_body<T, TC, BK>(ArgBufs{b}, t, c, s, blockIdx.x, gridDim.x);
+}
+
+// Grouped launch over several plans (independent solves advanced together):
+// work-group g runs plan p, wg_prefix[p] <= g < wg_prefix[p + 1], as its
+// work-group g - wg_prefix[p], with that plan's buffers and schedule.
+__device__ __forceinline__ int plan_of(const int32_t* __restrict__ prefix, int nplans, int g) {
+    int p = 0;
+    while (p + 1 < nplans && prefix[p + 1] <= g) ++p;
+    // uniform over the work-group: in a scalar register, so that the plan's
+    // descriptors are scalar loads as in the single-plan kernels
+    return __builtin_amdgcn_readfirstlane(p);
+}
+template <class T, class TC, int BK>
+__device__ __forceinline__ void multi_body(const PlanDesc* __restrict__ plans, const int32_t* __restrict__ prefix,
+                                           int nplans) {
+    const int p = plan_of(prefix, nplans, blockIdx.x);
+    // the buffer table stays in memory (a local copy indexed by the chunks'
+    // buffer numbers would live in scratch)
+    // the plan's fields, each a scalar load at its offset
+    const uintptr_t base = (uintptr_t)(plans + p);
+    auto u64 = [&](size_t off) { return *(const __attribute__((address_space(4))) uint64_t*)(base + off); };
+    auto i32 = [&](size_t off) { return *(const __attribute__((address_space(4))) int32_t*)(base + off); };
+    constexpr size_t bo = offsetof(PlanDesc, bufs), so = offsetof(PlanDesc, sc);
+    __shared__ Bufs tab;
+    if (threadIdx.x < kMaxBufs) tab.p[threadIdx.x] = (void*)u64(bo + 8 * threadIdx.x);
+    __syncthreads();
+    const LdsBufs b{&tab};
+    Sched sc;
+    sc.wg_off = (const int32_t*)u64(so + offsetof(Sched, wg_off));
+    sc.nwg = i32(so + offsetof(Sched, nwg));
+    sc.nfull = i32(so + offsetof(Sched, nfull));
+    sc.ntasks = i32(so + offsetof(Sched, ntasks));
+    gemm_body<T, TC, BK>(b, (const GemmTask*)u64(offsetof(PlanDesc, tasks)),
+                         (const GemmChunk*)u64(offsetof(PlanDesc, chunks)), sc, blockIdx.x - prefix[p],
+                         prefix[p + 1] - prefix[p]);
+}
+template <class T, class TC, int BK>
+__global__ void __launch_bounds__(NTH, 4) k_multi_gemm(const PlanDesc* p, const int32_t* x, int n) {
+    multi_body<T, TC, BK>(p, x, n);
+}
+template <class T, class TC, int BK>
+__global__ void __launch_bounds__(NTH, 4) k_multi_heff_z(const PlanDesc* p, const int32_t* x, int n) {
+    multi_body<T, TC, BK>(p, x, n);
+}
+template <class T, class TC, int BK>
+__global__ void __launch_bounds__(NTH, 4) k_multi_heff_y(const PlanDesc* p, const int32_t* x, int n) {
+    multi_body<T, TC, BK>(p, x, n);
+}
+
+int gemm_multi(Ctx* c, int ab, int cp, const PlanDesc* plans, const int32_t* prefix, int nplans, int total_wg,
+               int kind) {
+    if (nplans <= 0 || total_wg <= 0) return 0;
+    dim3 grid(total_wg), block(NTH);
+#define MULTI(T, TC, BK)                                                                                   \
+    do {                                                                                                   \
+        if (kind == GK_HEFF_Z)                                                                             \
+            hipLaunchKernelGGL((k_multi_heff_z<T, TC, BK>), grid, block, 0, c->stream, plans, prefix, nplans); \
+        else if (kind == GK_HEFF_Y)                                                                        \
+            hipLaunchKernelGGL((k_multi_heff_y<T, TC, BK>), grid, block, 0, c->stream, plans, prefix, nplans); \
+        else                                                                                               \
+            hipLaunchKernelGGL((k_multi_gemm<T, TC, BK>), grid, block, 0, c->stream, plans, prefix, nplans);  \
+    } while (0)
+    if (ab == P_F64 && cp == P_F64) MULTI(double, double, 16);
+    else if (ab == P_F32 && cp == P_F32) MULTI(float, float, 32);
+    else if (ab == P_BF16 && cp == P_F32) MULTI(bf16_t, float, 32);
+    else if (ab == P_BF16 && cp == P_BF16) MULTI(bf16_t, bf16_t, 32);
+    else {
+        c->err = "unsupported GEMM precision combination";
+        return 1;
+    }
+#undef MULTI
+    LAUNCHCHK(c);
+    return 0;
 }
 
 int gemm(Ctx* c, int ab, int cp, void* const* bufs, const GemmTask* tasks, const Sched& sc,
@@ -675,8 +874,7 @@ int gemm(Ctx* c, int ab, int cp, void* const* bufs, const GemmTask* tasks, const
 // slots in a fixed order (four interleaved partial sums, then combined), so
 // results are deterministic and many loads are in flight per thread.
 template <class TC>
-__global__ void __launch_bounds__(256) k_gemm_reduce(Bufs bufs, const RedTask* __restrict__ tasks) {
-    const RedTask tk = tasks[blockIdx.x];
+__device__ __forceinline__ void reduce_body(const Bufs& bufs, const RedTask& tk) {
     const int e = blockIdx.y * 256 + threadIdx.x;
     const int r = e / TN, c = e % TN;
     if (r >= tk.mt || c >= tk.nt) return;
@@ -694,6 +892,32 @@ __global__ void __launch_bounds__(256) k_gemm_reduce(Bufs bufs, const RedTask* _
     TC* d = (TC*)bufs.p[tk.dst_buf] + tk.dst_off + (int64_t)r * tk.ld + c;
     if (tk.beta) s += (double)*d;
     *d = (TC)s;
+}
+template <class TC>
+__global__ void __launch_bounds__(256) k_gemm_reduce(Bufs bufs, const RedTask* __restrict__ tasks) {
+    reduce_body<TC>(bufs, tasks[blockIdx.x]);
+}
+// reductions of several plans: block x is reduction x - prefix[p] of plan p
+template <class TC>
+__global__ void __launch_bounds__(256) k_gemm_reduce_multi(const RedDesc* __restrict__ plans,
+                                                           const int32_t* __restrict__ prefix, int nplans) {
+    const int p = plan_of(prefix, nplans, blockIdx.x);
+    reduce_body<TC>(*reinterpret_cast<const Bufs*>(plans[p].bufs), plans[p].reds[blockIdx.x - prefix[p]]);
+}
+
+int gemm_reduce_multi(Ctx* c, int cp, const RedDesc* plans, const int32_t* prefix, int nplans, int total) {
+    if (nplans <= 0 || total <= 0) return 0;
+    dim3 grid(total, TM * TN / 256);
+    if (cp == P_F64)
+        hipLaunchKernelGGL(k_gemm_reduce_multi<double>, grid, dim3(256), 0, c->stream, plans, prefix, nplans);
+    else if (cp == P_F32)
+        hipLaunchKernelGGL(k_gemm_reduce_multi<float>, grid, dim3(256), 0, c->stream, plans, prefix, nplans);
+    else {
+        c->err = "split-K reduction supports FP64 and FP32 outputs";
+        return 1;
+    }
+    LAUNCHCHK(c);
+    return 0;
 }
 
 int gemm_reduce(Ctx* c, int cp, void* const* bufs, const RedTask* tasks, int ntasks) {

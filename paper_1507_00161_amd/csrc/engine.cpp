@@ -13,6 +13,8 @@
 //   the state is carried to the next bond as the next initial guess.
 #include "engine.h"
 
+#include "batch.h"
+
 #include <algorithm>
 #include <cstdio>
 #include <chrono>
@@ -150,6 +152,9 @@ template <class T> dmrg_status Engine::upload(Buf& b, const std::vector<T>& v) {
 }
 
 Engine::~Engine() {
+    dmrgdev::graph_destroy(graph_exec_);
+    dmrgdev::xevent_destroy(ev_ready_);
+    dmrgdev::xevent_destroy(ev_done_);
     dying_ = true;   // buffers released from here on go straight back to the device
     cur_.reset();
     L_.clear();
@@ -603,6 +608,7 @@ dmrg_status Engine::load(int n, const int32_t* species, const int32_t* two_m, co
     psi1_.reset();
     init_ = false;
     loaded_ = false;
+    cideas_ = false;
     meas_valid_ = false;
     have_energy_ = false;
     sweeps_done_ = 0;
@@ -1349,6 +1355,7 @@ dmrg_status Engine::setup_bond(int b, std::unique_ptr<Bond>& outp) {
     double t0 = now();
     auto B = std::make_unique<Bond>();
     B->b = b;
+    B->gen = ++bond_gen_;
     const Stored& L = *L_[b];
     const Stored& R = *R_[b + 2];
     // E sectors: complementable by the sites 0..b
@@ -1818,6 +1825,55 @@ dmrg_status Engine::heff(Bond& B, const double* x, double* y, int prec) {
 // one product with per-phase event timing (the events add no synchronisation;
 // the elapsed times are read after the product completes)
 dmrg_status Engine::heff_launch(Bond& B, const double* x, double* y, int prec, bool timed) {
+    if (batch_ && B.groups.size() == 1) return heff_batched(B, x, y, prec);
+    if (opt_.graph && B.groups.size() == 1) return heff_graph(B, x, y, prec);
+    return heff_direct(B, x, y, prec, timed);
+}
+
+// The bond's product as a HIP graph: captured at the bond's first product in
+// this precision, after every buffer it touches has its final size (nothing
+// is allocated or synchronised during the capture), and replayed for later
+// products; x and y pass through fixed staging vectors.
+dmrg_status Engine::heff_graph(Bond& B, const double* x, double* y, int prec) {
+    if (graph_exec_ && (graph_gen_ != B.gen || graph_prec_ != prec)) {
+        dmrgdev::graph_destroy(graph_exec_);
+        graph_exec_ = nullptr;
+    }
+    if (!graph_exec_) {
+        const size_t vb = (size_t)std::max<int64_t>(B.dim, 1) * sizeof(double);
+        if (gin_.bytes < vb) TRY(alloc_buf(gin_, vb));
+        if (gout_.bytes < vb) TRY(alloc_buf(gout_, vb));
+        const HeffGroup& g = B.groups[0];
+        if (prec != dmrgdev::P_F64) {
+            TRY(ensure_lo(B, prec));
+            const size_t esz = prec == dmrgdev::P_F32 ? 4 : 2;
+            if (xlo_.bytes < (size_t)B.dim * esz) TRY(alloc_buf(xlo_, std::max<int64_t>(B.dim, 1) * esz));
+            if (ylo_.bytes < (size_t)B.dim * 4) TRY(alloc_buf(ylo_, std::max<int64_t>(B.dim, 1) * 4));
+            const size_t zbytes = (size_t)std::max<int64_t>(g.z_elems, 1) * esz;
+            if (scr_a_.bytes < zbytes) TRY(alloc_buf(scr_a_, zbytes));
+        }
+        const int64_t slots = std::max({g.p1.nslots, g.p2.nslots, g.p3.nslots});
+        if (slots) TRY(ensure_partials(slots));
+        DEV(dmrgdev::graph_begin(dev_));
+        dmrg_status st = heff_direct(B, gin_.d(), gout_.d(), prec, false);
+        void* ex = nullptr;
+        const int rc = dmrgdev::graph_end(dev_, &ex);
+        if (st < 0) {
+            dmrgdev::graph_destroy(ex);
+            return st;
+        }
+        if (rc) return fail(DMRG_ERR_DEVICE, dmrgdev::last_error(dev_));
+        graph_exec_ = ex;
+        graph_gen_ = B.gen;
+        graph_prec_ = prec;
+    }
+    DEV(dmrgdev::d2d(dev_, gin_.p, x, (size_t)B.dim * sizeof(double)));
+    DEV(dmrgdev::graph_launch(dev_, graph_exec_));
+    DEV(dmrgdev::d2d(dev_, y, gout_.p, (size_t)B.dim * sizeof(double)));
+    return DMRG_OK;
+}
+
+dmrg_status Engine::heff_direct(Bond& B, const double* x, double* y, int prec, bool timed) {
     const double es = prec == dmrgdev::P_F64 ? 8.0 : (prec == dmrgdev::P_F32 ? 4.0 : 2.0);
     if (prec == dmrgdev::P_F64) {
         for (size_t g = 0; g < B.groups.size(); ++g) {
@@ -1852,6 +1908,60 @@ dmrg_status Engine::heff_launch(Bond& B, const double* x, double* y, int prec, b
         if (timed) account(B.groups[g], es, es);
     }
     DEV(dmrgdev::convert(dev_, dmrgdev::P_F32, ylo_.p, dmrgdev::P_F64, y, B.dim));
+    return DMRG_OK;
+}
+
+// The product of heff_launch through the batch: the input conversion and the
+// output conversion stay on the context stream; the three GEMM phases and
+// their reductions are launched by the batch together with the products of
+// the other contexts pending at the time (same plans, same buffers).
+dmrg_status Engine::heff_batched(Bond& B, const double* x, double* y, int prec) {
+    const HeffGroup& g = B.groups[0];
+    BufTable bufs{};
+    int cp1 = prec, cp2 = prec;
+    const bool low = prec != dmrgdev::P_F64;
+    if (!low) {
+        bufs = BufTable{B.Sops.pool.p, B.Eops.pool.p, (void*)x, z_.p, y};
+    } else {
+        TRY(ensure_lo(B, prec));
+        const size_t esz = prec == dmrgdev::P_F32 ? 4 : 2;
+        if (xlo_.bytes < (size_t)B.dim * esz) TRY(alloc_buf(xlo_, std::max<int64_t>(B.dim, 1) * esz));
+        if (ylo_.bytes < (size_t)B.dim * 4) TRY(alloc_buf(ylo_, std::max<int64_t>(B.dim, 1) * 4));
+        const size_t zbytes = (size_t)std::max<int64_t>(g.z_elems, 1) * esz;
+        if (scr_a_.bytes < zbytes) TRY(alloc_buf(scr_a_, zbytes));
+        DEV(dmrgdev::convert(dev_, dmrgdev::P_F64, x, prec, xlo_.p, B.dim));
+        bufs = BufTable{B.Sops.pool_lo.p, B.Eops.pool_lo.p, xlo_.p, scr_a_.p, ylo_.p};
+        cp2 = dmrgdev::P_F32;
+    }
+    const int64_t slots = std::max({g.p1.nslots, g.p2.nslots, g.p3.nslots});
+    if (slots) {
+        TRY(ensure_partials(slots));
+        bufs[dmrgdev::kPartialBuf] = partial_.p;
+    }
+    if (!ev_ready_) ev_ready_ = dmrgdev::xevent_create(dev_);
+    if (!ev_done_) ev_done_ = dmrgdev::xevent_create(dev_);
+    if (!ev_ready_ || !ev_done_) return fail(DMRG_ERR_DEVICE, dmrgdev::last_error(dev_));
+    HeffRequest r;
+    r.ab_prec = prec;
+    r.c_prec[0] = cp1;
+    r.c_prec[1] = r.c_prec[2] = cp2;
+    const GemmPlan* ps[3] = {&g.p1, &g.p2, &g.p3};
+    for (int ph = 0; ph < 3; ++ph) {
+        const GemmPlan& p = *ps[ph];
+        for (int i = 0; i < dmrgdev::kMaxBufs; ++i) r.plan[ph].bufs[i] = r.red[ph].bufs[i] = bufs[i];
+        r.plan[ph].tasks = p.tasks.as<GemmTask>();
+        r.plan[ph].chunks = p.chunks.as<GemmChunk>();
+        r.plan[ph].sc = dmrgdev::Sched{p.wg_off.as<int32_t>(), std::max(1, p.nwg), p.nfull, p.ntasks};
+        r.nwg[ph] = p.ntasks ? std::max(1, p.nwg) : 0;
+        r.red[ph].reds = p.reds.as<dmrgdev::RedTask>();
+        r.nreds[ph] = p.nreds;
+    }
+    r.ready = ev_ready_;
+    r.done = ev_done_;
+    DEV(dmrgdev::xevent_record(dev_, ev_ready_));
+    if (batch_->run(r)) return fail(DMRG_ERR_DEVICE, "grouped launch: " + batch_->error());
+    DEV(dmrgdev::xevent_wait(dev_, ev_done_));
+    if (low) DEV(dmrgdev::convert(dev_, dmrgdev::P_F32, ylo_.p, dmrgdev::P_F64, y, B.dim));
     return DMRG_OK;
 }
 
@@ -2146,8 +2256,137 @@ std::vector<std::vector<double>> Engine::selection_iso(const std::vector<int>& d
     return iso;
 }
 
+// CI-DEAS environment block (the block-state paragraph cites a CI-based,
+// dynamically extended active space grown by the orbital entropy profile).
+// The block R = sites lo..N-1 keeps determinants of its composite basis (site
+// lo times the block built before it, whose states are determinants): those
+// differing from the reference determinant only on its k most entropic sites
+// (decreasing one-orbital entropy, ties to the lower position), for the
+// largest k whose CI space holds at most D determinants, completed to D from
+// the next space with the fewest differing sites first, then the SplitMix64
+// key (seed, 5, lo, low and high 32 bits of the determinant).  Kept rows are
+// in basis order; the isometry is a selection.
+std::vector<std::vector<double>> Engine::cideas_iso(const Enl& comp, const Stored& base, int D, int lo,
+                                                    std::vector<int>& kept,
+                                                    std::vector<std::vector<int>>& chosen) {
+    const size_t ns = comp.mq.size();
+    std::vector<int> rank(N_, 0);   // 1-based rank among the block's sites by entropy
+    {
+        std::vector<int> sites;
+        for (int i = lo; i < N_; ++i) sites.push_back(i);
+        std::stable_sort(sites.begin(), sites.end(),
+                         [&](int a, int b) { return cd_s_[a] != cd_s_[b] ? cd_s_[a] > cd_s_[b] : a < b; });
+        for (size_t k = 0; k < sites.size(); ++k) rank[sites[k]] = (int)k + 1;
+    }
+    const uint64_t mask = (N_ >= 64 ? ~0ull : ((1ull << N_) - 1)) & ~((1ull << lo) - 1);
+    struct Cand {
+        int level, pc;
+        uint64_t key;
+        int m, row;
+    };
+    std::vector<Cand> cand;
+    for (size_t m = 0; m < ns; ++m) {
+        int row = 0;
+        for (int sg = 0; sg < 2; ++sg) {
+            const int si = comp.msub[m][sg];
+            if (si < 0) continue;
+            for (uint64_t c0 : base.cfg[comp.sub[si].base]) {
+                const uint64_t c = c0 | (sg ? (1ull << lo) : 0ull);
+                const uint64_t d = (c ^ cd_ref_) & mask;
+                int level = 0;
+                for (int i = lo; i < N_; ++i)
+                    if ((d >> i) & 1ull) level = std::max(level, rank[i]);
+                const uint64_t key = hkey({(int64_t)opt_.seed, 5, lo, (int64_t)(c & 0xffffffffull), (int64_t)(c >> 32)});
+                cand.push_back({level, __builtin_popcountll(d), key, (int)m, row++});
+            }
+        }
+    }
+    std::vector<char> keep(cand.size(), 0);
+    if ((int64_t)cand.size() <= D) {
+        std::fill(keep.begin(), keep.end(), 1);
+    } else {
+        std::vector<int64_t> count(N_ - lo + 2, 0);
+        for (const Cand& c : cand) count[c.level]++;
+        int kstar = -1;
+        int64_t cum = 0;
+        for (int k = 0; k <= N_ - lo; ++k) {
+            if (cum + count[k] > D) break;
+            cum += count[k];
+            kstar = k;
+        }
+        std::vector<size_t> nxt;
+        for (size_t x = 0; x < cand.size(); ++x) {
+            if (cand[x].level <= kstar) keep[x] = 1;
+            else if (cand[x].level == kstar + 1) nxt.push_back(x);
+        }
+        std::sort(nxt.begin(), nxt.end(), [&](size_t a, size_t b) {
+            if (cand[a].pc != cand[b].pc) return cand[a].pc < cand[b].pc;
+            return cand[a].key < cand[b].key;
+        });
+        for (size_t y = 0; y < nxt.size() && cum < D; ++y, ++cum) keep[nxt[y]] = 1;
+    }
+    kept.assign(ns, 0);
+    chosen.assign(ns, {});
+    for (size_t x = 0; x < cand.size(); ++x)
+        if (keep[x]) chosen[cand[x].m].push_back(cand[x].row);
+    std::vector<std::vector<double>> iso(ns);
+    for (size_t m = 0; m < ns; ++m) {
+        auto& ch = chosen[m];
+        std::sort(ch.begin(), ch.end());
+        const int d = comp.md[m], k = (int)ch.size();
+        kept[m] = k;
+        if (!k) continue;
+        std::vector<double> U((size_t)d * k, 0.0);
+        for (int c = 0; c < k; ++c) U[(size_t)ch[c] * k + c] = 1.0;
+        iso[m] = std::move(U);
+    }
+    return iso;
+}
+
+dmrg_status Engine::set_cideas(const double* s1, const double* n1) {
+    if (!loaded_) return fail(DMRG_ERR_STATE, "no Hamiltonian loaded");
+    if (!s1 && !n1) {
+        cideas_ = false;
+        init_ = false;
+        return DMRG_OK;
+    }
+    if (!s1 || !n1) return fail(DMRG_ERR_ARG, "give both the entropies and the occupations, or neither");
+    // measured values carry rounding (an occupation of 1 + 4e-16); only their order is used
+    const double slack = 1e-9;
+    for (int i = 0; i < N_; ++i)
+        if (!std::isfinite(s1[i]) || s1[i] < -slack || !std::isfinite(n1[i]) || n1[i] < -slack ||
+            n1[i] > 1.0 + slack)
+            return fail(DMRG_ERR_ARG, "entropies must be finite and >= 0, occupations in [0, 1] (within 1e-9)");
+    cds_site_.assign(s1, s1 + N_);
+    cdn_site_.assign(n1, n1 + N_);
+    cideas_ = true;
+    init_ = false;   // the next sweep starts from CI-DEAS blocks
+    return DMRG_OK;
+}
+
+// chain-position profile and reference determinant of the CI-DEAS start
+void Engine::cideas_chain() {
+    cd_s_.assign(N_, 0.0);
+    std::vector<double> occ(N_);
+    for (int a = 0; a < N_; ++a) {
+        cd_s_[a] = cds_site_[order_[a]];
+        occ[a] = cdn_site_[order_[a]];
+    }
+    cd_ref_ = 0;
+    for (int sp = 0; sp < 2; ++sp) {
+        std::vector<int> sites;
+        for (int a = 0; a < N_; ++a)
+            if ((sp == 0) == (delta_[a].np == 1)) sites.push_back(a);
+        std::stable_sort(sites.begin(), sites.end(),
+                         [&](int a, int b) { return occ[a] != occ[b] ? occ[a] > occ[b] : a < b; });
+        const int cnt = sp == 0 ? T_.np : T_.nn;
+        for (int x = 0; x < cnt && x < (int)sites.size(); ++x) cd_ref_ |= 1ull << sites[x];
+    }
+}
+
 // ============================================================ initialise
 dmrg_status Engine::initialize(int D) {
+    if (cideas_) cideas_chain();
     cur_.reset();
     psi_.reset();
     psi1_.reset();
@@ -2174,7 +2413,8 @@ dmrg_status Engine::initialize(int D) {
         TRY(enlarge(base, 'R', allowed, blk->comp, eops));
         std::vector<int> kept;
         std::vector<std::vector<int>> chosen;
-        auto iso = selection_iso(blk->comp.md, D, 1, lo, blk->comp.mq, !opt_.select_basis, kept, &chosen);
+        auto iso = cideas_ ? cideas_iso(blk->comp, base, D, lo, kept, chosen)
+                           : selection_iso(blk->comp.md, D, 1, lo, blk->comp.mq, !opt_.select_basis, kept, &chosen);
         std::vector<int> keep_m, kdim;
         std::vector<double> flat;
         for (size_t m = 0; m < kept.size(); ++m) {
@@ -2191,7 +2431,7 @@ dmrg_status Engine::initialize(int D) {
         TRY(upload(blk->iso, flat));
         bool normal_in = !normal_S(lo - 1);
         TRY(renormalize(blk->comp, eops, normal_in, *blk, keep_m, kdim));
-        if (opt_.select_basis && base.has_cfg) {
+        if ((opt_.select_basis || cideas_) && base.has_cfg) {
             blk->has_cfg = true;
             for (size_t x = 0; x < keep_m.size(); ++x) {
                 int m = keep_m[x];

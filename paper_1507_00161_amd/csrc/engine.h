@@ -232,6 +232,7 @@ struct HeffGroup {
 
 struct Bond {
     int b = 0;
+    int64_t gen = 0;      // distinct for every bond set up by a context
     Enl S, E;
     OpSet Sops, Eops;
     // psi layout: merged S sector pm_S[x] with E sector pm_E[x], offset poff[x]
@@ -248,6 +249,7 @@ struct Bond {
 };
 
 struct LB;   // linear-combination task builder (engine.cpp)
+class Batch;  // products of several contexts launched together (batch.h)
 
 class Engine {
 public:
@@ -266,6 +268,9 @@ public:
     dmrg_status configs(uint64_t* out);
     dmrg_status orbital_entropies(double* s1, double* mutual, double* n1, double* nn, double* hop);
     bool measuring() const { return opt_.measure != 0; }
+    dmrg_status set_cideas(const double* s1, const double* n1);
+    // while set, H_eff products of single-group bonds go through the batch
+    void attach_batch(Batch* b) { batch_ = b; }
     dmrg_status set_check_fp64(bool on) {
         check_fp64_ = on;
         return DMRG_OK;
@@ -347,6 +352,18 @@ private:
     Buf z_, xlo_, ylo_, scr_a_, scr_b_, scal_;
     double heff_time_ = 0.0;   // device seconds of H_eff products in the current solve
     bool check_fp64_ = false;  // repeat mixed solves in FP64 (diagnostic)
+    Batch* batch_ = nullptr;
+    void* ev_ready_ = nullptr;  // product input ready (context stream)
+    void* ev_done_ = nullptr;   // product launched (batch stream)
+    dmrg_status heff_batched(Bond& B, const double* x, double* y, int prec);
+    // HIP graph of the current bond's product (option graph)
+    int64_t bond_gen_ = 0;
+    void* graph_exec_ = nullptr;
+    int64_t graph_gen_ = -1;
+    int graph_prec_ = -1;
+    Buf gin_, gout_;
+    dmrg_status heff_graph(Bond& B, const double* x, double* y, int prec);
+    dmrg_status heff_direct(Bond& B, const double* x, double* y, int prec, bool timed);
     bool force_fp64_ = false;  // the solve in progress uses FP64 products only
     Buf chk_psi_;              // guess kept for the repeat
 
@@ -390,6 +407,13 @@ private:
     void reset_measure();
     std::vector<double> m_n1_, m_pni_, m_pnj_, m_nn_, m_hop_;
     bool meas_valid_ = false;
+    // CI-DEAS start: profile in site indices, in chain positions, reference determinant
+    bool cideas_ = false;
+    std::vector<double> cds_site_, cdn_site_, cd_s_;
+    uint64_t cd_ref_ = 0;
+    void cideas_chain();
+    std::vector<std::vector<double>> cideas_iso(const Enl& comp, const Stored& base, int D, int lo,
+                                                std::vector<int>& kept, std::vector<std::vector<int>>& chosen);
     std::vector<std::vector<double>> selection_iso(const std::vector<int>& dims, int D, int tag,
                                                    int pos, const std::vector<QN>& qs, bool mix,
                                                    std::vector<int>& kept,

@@ -10,6 +10,7 @@ schedule, ordering and options and compare energies (relative 1e-8 in FP64,
     python tests/golden/make_golden.py                 all cases of CASES
     python tests/golden/make_golden.py NAME ...        only those cases (merged into the file)
     python tests/golden/make_golden.py --bench-schedule
+    python tests/golden/make_golden.py --batched 64
 
 --bench-schedule writes oracle_bench_schedule.json: the benchmark's own
 workload (pf 8p+8n), options and D schedule (512, 512, 1024, 1024, then
@@ -55,7 +56,25 @@ CASES = [
     ("pf_8p8n_ent", "pf_8p8n", None, [32, 32], {"measure": True}),
     ("sd_4p4n_two_ent", "sd_4p4n", None, [32, 32], {"measure": True, "n_states": 2}),
     ("sd_4p4n_dbss_ent", "sd_4p4n", None, [128, 128], {"measure": True, "trunc_eps": 1e-3, "d_min": 8}),
+    # CI-DEAS start: entropies and occupations from a measuring run (2 sweeps at D = 16)
+    ("p_2p2n_cideas", "p_2p2n", 3, [16, 16], {"cideas": 16}),
+    ("sd_4p4n_cideas", "sd_4p4n", None, [32, 32], {"cideas": 16}),
+    ("pf_8p8n_cideas", "pf_8p8n", None, [32, 32], {"cideas": 16}),
 ]
+
+
+def cideas_profile(h, order, D):
+    """(s1, n1) in site indices from two measuring sweeps of the oracle at D."""
+    sp = h.space
+    m = dmrg.DMRG(h.eps, h.V, sp.species, sp.two_m, h.n_p, h.n_n, h.two_M, order,
+                  dmrg.Options(**OPTS, measure=True))
+    for _ in range(2):
+        m.sweep(D)
+    s1, _, raw = m.entropies()
+    n1 = [0.0] * sp.n_sites
+    for pos, site in enumerate(m.order):
+        n1[int(site)] = float(raw["n1"][pos])
+    return [float(x) for x in s1], n1
 
 
 def hamiltonian(spec):
@@ -90,9 +109,39 @@ def bench_schedule():
         print(f"bench schedule D={D}: {r['energy']} ({time.time() - t:.0f} s)", flush=True)
 
 
+# the independent small solves advanced together by dmrg_sweep_many (one
+# sweep each at the instance's D, mixed-mode options of bench.py --batched)
+BATCH_OPTS = dict(davidson_tol=1e-7, noise=1e-4, noise_sweeps=1, seed=1507)
+
+
+def batched(count):
+    """oracle_batched.json: the first sweep energy of each of the first
+    `count` seeded instances whose oracle sweep is cheap (p and sd spaces at
+    every D, pf at D <= 128)."""
+    from workloads import batched_instances
+    out = {"options": BATCH_OPTS, "count": count, "instances": {}}
+    path = os.path.join(HERE, "oracle_batched.json")
+    for i, w in enumerate(batched_instances(count)):
+        D = w.D_schedule[0]
+        if w.space == "pf" and D > 128:
+            continue
+        h = w.hamiltonian()
+        sp = h.space
+        t = time.time()
+        o = dmrg.DMRG(h.eps, h.V, sp.species, sp.two_m, h.n_p, h.n_n, h.two_M, None, dmrg.Options(**BATCH_OPTS))
+        r = o.sweep(D)
+        out["instances"][str(i)] = {"space": w.space, "n_p": h.n_p, "n_n": h.n_n, "D": D, "energy": r["energy"]}
+        with open(path, "w") as f:
+            json.dump(out, f, indent=1)
+        print(f"instance {i} {w.space} {h.n_p}p{h.n_n}n D={D}: {r['energy']} ({time.time() - t:.1f} s)", flush=True)
+
+
 def main():
     if sys.argv[1:] == ["--bench-schedule"]:
         bench_schedule()
+        return
+    if sys.argv[1:2] == ["--batched"]:
+        batched(int(sys.argv[2]))
         return
     only = set(sys.argv[1:])
     path = os.path.join(HERE, "oracle_energies.json")
@@ -108,14 +157,21 @@ def main():
         sp = h.space
         order = None if oseed is None else random_ordering(sp.n_sites, oseed)
         t = time.time()
+        opts = dict(extra)
+        prof = None
+        if "cideas" in opts:
+            prof = cideas_profile(h, order, opts.pop("cideas"))
+            opts.update(cideas_entropy=prof[0], cideas_occupation=prof[1])
         o = dmrg.DMRG(h.eps, h.V, sp.species, sp.two_m, h.n_p, h.n_n, h.two_M, order,
-                      dmrg.Options(**OPTS, **extra))
+                      dmrg.Options(**OPTS, **opts))
         res = [o.sweep(D) for D in sched]
         energies = [r["energy"] for r in res]
         case = {"workload": spec, "ordering_seed": oseed, "D": sched, "energies": energies,
                 "kept_max": [r["kept_max"] for r in res], "options": extra,
                 "energies_excited": [r.get("energy_excited") for r in res],
                 "target": [h.n_p, h.n_n, h.two_M]}
+        if prof is not None:
+            case["cideas_s1"], case["cideas_n1"] = prof
         if extra.get("measure"):
             s1, mutual, m = o.entropies()
             case["s1"] = s1.tolist()

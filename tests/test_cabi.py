@@ -46,7 +46,7 @@ def test_default_options(lib):
     assert o.precision == 0 and o.seed == 1507
     assert o.davidson_tol == 1e-7 and o.davidson_max_iter == 100 and o.davidson_max_subspace == 24
     assert o.tie_tol == 1e-13 and o.noise == 0.0 and o.select_basis == 0
-    assert o.trunc_eps == 0.0 and o.d_min == 0 and o.n_states == 1 and o.measure == 0
+    assert o.trunc_eps == 0.0 and o.d_min == 0 and o.n_states == 1 and o.measure == 0 and o.graph == 0
 
 
 def test_status_strings(lib):

@@ -151,3 +151,21 @@ def test_check_fp64_rejects_bad_argument(pk):
     assert c._lib.dmrg_check_fp64(None, 1) == -1
     c.check_fp64(True)
     c.check_fp64(False)
+
+
+def test_set_cideas_errors(pk):
+    h = _h()
+    c = pk.Context()
+    s = np.full(h.space.n_sites, 0.3)
+    n = np.full(h.space.n_sites, 0.5)
+    sa, na = pk._f64(s), pk._f64(n)
+    assert c._lib.dmrg_set_cideas(c._h, pk._ptr(sa), pk._ptr(na)) == -4    # no Hamiltonian yet
+    _load(c, h)
+    assert c._lib.dmrg_set_cideas(c._h, pk._ptr(pk._f64(s)), None) == -1
+    bad = s.copy()
+    bad[3] = -1.0
+    with pytest.raises(pk.DMRGError) as e:
+        c.set_cideas(bad, n)
+    assert e.value.status == -1
+    c.set_cideas(s, n)
+    c.set_cideas(None, None)

@@ -221,7 +221,8 @@ def _golden_ham(spec):
 
 
 @pytest.mark.parametrize("name", ["p_2p2n_D64", "p_2p2n_M2_D16", "sd_4p4n_D32", "sd_3p2n_M1_rand_D24",
-                                  "pf_8p8n_D32", "pfg9_12p12n_D16", "pfg9_12p12n_M2_D16"])
+                                  "pf_8p8n_D32", "pfg9_12p12n_D16", "pfg9_12p12n_M2_D16",
+                                  "pfg9_12p12n_D64", "pfg9_12p12n_M2_D64"])
 @pytest.mark.parametrize("precision,rtol", [(0, 1e-8), (1, 1e-6), (2, 1e-6)])
 def test_sweep_energies_match_oracle(pk, name, precision, rtol):
     g = _golden()
@@ -237,6 +238,45 @@ def test_sweep_energies_match_oracle(pk, name, precision, rtol):
         if "exact" in case:
             assert r["energy"] >= case["exact"] - 1e-9        # variational bound
     assert c.energy() == r["energy"]
+
+
+@pytest.mark.parametrize("precision,rtol", [(0, 1e-8), (1, 1e-6)])
+def test_benchmark_schedule_matches_oracle(pk, precision, rtol):
+    """The benchmark's own workload and schedule (pf 8p+8n, the 56Ni-sized
+    space; D = 512, 512, 1024, 1024, then 2048; the benchmark's options):
+    every sweep energy against the oracle's on the same schedule
+    (tests/golden/oracle_bench_schedule.json), FP64 to 1e-8 and mixed FP32
+    to 1e-6 relative."""
+    path = os.path.join(os.path.dirname(__file__), "golden", "oracle_bench_schedule.json")
+    with open(path) as f:
+        g = json.load(f)
+    assert g["workload"] == "pf_8p8n" and len(g["D"]) >= 5
+    h = WORKLOADS["pf_8p8n"].hamiltonian()
+    c = _ctx(pk, h, precision=precision, **g["options"])
+    for k, (D, e_ref) in enumerate(zip(g["D"], g["energies"])):
+        r = c.sweep(D)
+        assert r["code"] in (0, 1)       # the first sweep from the hash start may hit the product limit
+        assert abs(r["energy"] - e_ref) <= rtol * abs(e_ref), (k, D, r["energy"], e_ref)
+
+
+@pytest.mark.parametrize("name", ["p_2p2n_cideas", "sd_4p4n_cideas", "pf_8p8n_cideas"])
+@pytest.mark.parametrize("precision,rtol", [(0, 1e-8), (1, 1e-6)])
+def test_cideas_sweeps_match_oracle(pk, name, precision, rtol):
+    """The CI-DEAS start (environment blocks from the CI spaces of an active
+    space grown by the entropy profile of a measuring run, the profile stored
+    with the case): sweep energies equal the oracle's."""
+    g = _golden()
+    case = g["cases"][name]
+    h = _golden_ham(case["workload"])
+    sp = h.space
+    order = None if case["ordering_seed"] is None else random_ordering(sp.n_sites, case["ordering_seed"])
+    opts = {k: v for k, v in case["options"].items() if k != "cideas"}
+    c = _ctx(pk, h, precision=precision, **g["options"], **opts)
+    c.set_cideas(case["cideas_s1"], case["cideas_n1"])
+    for D, e_ref in zip(case["D"], case["energies"]):
+        r = c.sweep(D, order)
+        assert r["code"] in (0, 1)
+        assert abs(r["energy"] - e_ref) <= rtol * abs(e_ref), (D, r["energy"], e_ref)
 
 
 @pytest.mark.parametrize("name", ["p_2p2n_dbss", "sd_4p4n_dbss"])
@@ -453,6 +493,57 @@ def test_entropies_full_size_pf_8p8n_D2048(pk):
         assert n1.min() >= -1e-12 and n1.max() <= 1.0 + 1e-12
         assert abs(n1[:20].sum() - 8.0) < 0.05 and abs(n1[20:].sum() - 8.0) < 0.05
         assert (np.abs(hop) <= 0.5 + 1e-12).all()   # |<c+_i c_j>| <= sqrt(<n_i><1 - n_j>)-type bound
+
+
+@pytest.mark.parametrize("precision,rtol", [(0, 1e-8), (1, 1e-6)])
+def test_sweep_many_matches_oracle_batched(pk, precision, rtol):
+    """The independent small solves of the batched workload (seeded p, sd and
+    pf instances, 2..8 particles per species, D from 64 to 512), advanced
+    together by dmrg_sweep_many with their products launched in groups: the
+    first-sweep energy of every instance the oracle has
+    (tests/golden/oracle_batched.json: p and sd at every D, pf at D <= 128)."""
+    from workloads import batched_instances
+    path = os.path.join(os.path.dirname(__file__), "golden", "oracle_batched.json")
+    with open(path) as f:
+        g = json.load(f)
+    ws = batched_instances(g["count"])
+    idx = sorted(int(i) for i in g["instances"])
+    assert len(idx) >= 20
+    ctxs = [_ctx(pk, ws[i].hamiltonian(), precision=precision, **g["options"]) for i in idx]
+    st, out = pk.sweep_many(ctxs, [ws[i].D_schedule[0] for i in idx])
+    assert st in (0, 1)
+    for i, o in zip(idx, out):
+        e_ref = g["instances"][str(i)]["energy"]
+        assert o["status"] in (0, 1)
+        assert abs(o["energy"] - e_ref) <= rtol * abs(e_ref), (i, o["energy"], e_ref)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_graph_products_match_direct_launches(pk, torch_dev, precision):
+    """Option graph (each bond's product captured once in a HIP graph and
+    replayed): sweeps are bit-identical to direct launches, and repeated
+    products at one bond, with eager work and synchronisations between the
+    replays, each equal the direct product exactly."""
+    import torch
+    h = WORKLOADS["sd_4p4n"].hamiltonian()
+    opts = dict(precision=precision, davidson_tol=1e-8, noise=1e-4, noise_sweeps=1, seed=4)
+    a, b = _ctx(pk, h, **opts), _ctx(pk, h, graph=1, **opts)
+    for D in (32, 48):
+        ra, rb = a.sweep(D), b.sweep(D)
+        assert ra["energy"] == rb["energy"] and ra["products_low"] == rb["products_low"]
+    a.sweep_steps(48, 9)
+    b.sweep_steps(48, 9)
+    _, dim, _, _ = a.heff_layout()
+    rng = np.random.default_rng(5)
+    for k in range(4):
+        x = torch.tensor(rng.normal(size=dim), device=torch_dev)
+        ya, yb = torch.empty_like(x), torch.empty_like(x)
+        a.heff_apply(x, ya, precision)
+        b.heff_apply(x, yb, precision)
+        z = (x * 2.0).sum()            # eager work between the replays
+        torch.cuda.synchronize()
+        assert torch.isfinite(z)
+        assert torch.equal(ya, yb), k
 
 
 def test_sweep_many_matches_single_contexts(pk):
