@@ -678,6 +678,9 @@ __device__ __forceinline__ void gemm_body(const BS bufs, const GemmTask* __restr
             // ragged sector blocks cost what they contain.
             const int kv = ch.K - k0;
             const bool am1 = wm + 16 < tk.mt, bm1 = wn + 16 < tk.nt;
+            // Full blocks: the next slice goes into the other LDS buffer halfway
+            // through the MFMAs, whose queue then covers the stores.
+            bool stored = false;
             if (kv >= BK && am1 && bm1) {
 #pragma unroll
                 for (int q = 0; q < NS; ++q) {
@@ -687,6 +690,10 @@ __device__ __forceinline__ void gemm_body(const BS bufs, const GemmTask* __restr
 #pragma unroll
                         for (int b = 0; b < 2; ++b)
                             acc[a][b] = MmaTraits<T>::mma(av[q % NF][a], bv[q % NF][b], acc[a][b]);
+                    if (q == NS / 2 - 1 && more) {
+                        store(nch, buf ^ 1);
+                        stored = true;
+                    }
                 }
             } else if (wm < tk.mt && wn < tk.nt) {
 #pragma unroll
@@ -712,7 +719,7 @@ __device__ __forceinline__ void gemm_body(const BS bufs, const GemmTask* __restr
                     }
                 }
             }
-            if (more) store(nch, buf ^ 1);
+            if (more && !stored) store(nch, buf ^ 1);
             __syncthreads();
             if (!more) break;
             tk = ntk;
@@ -941,33 +948,50 @@ struct DBufs {
     double* p[kMaxBufs];
 };
 
+// One 32 x 32 tile of D = sum_t coef_t op(S_t) per work-group; a thread owns
+// the elements e = tid + 256 u (row e / 32, column e % 32), so that a wave
+// reads two 32-element rows of a plain source.  A transposed source is read
+// along its own contiguous dimension and turned round in LDS.  Each element
+// sums its terms in term order.
 __global__ void __launch_bounds__(256) k_lincomb(DBufs bufs, const LcTask* __restrict__ tasks,
                                                  const LcTerm* __restrict__ terms) {
+    __shared__ double T[kLcTile][kLcTile + 1];
     const LcTask tk = tasks[blockIdx.x];
     const int tid = threadIdx.x;
-    const int r = tid >> 3, c4 = (tid & 7) * 4;   // 32 rows x 32 cols, 4 per thread
     double acc[4] = {0, 0, 0, 0};
     for (int t = tk.t_begin; t < tk.t_end; ++t) {
         const LcTerm L = terms[t];
-        const int rr = tk.r0 + r;
+        const double* S = L.ident ? nullptr : bufs.p[L.buf] + L.src_off;
+        if (L.trans && !L.ident) {
+            __syncthreads();   // the previous transposed term's readers are done
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int cc = tk.c0 + c4 + u;
-            if (r >= tk.mt || c4 + u >= tk.nt) continue;
-            double v;
-            if (L.ident) {
-                v = rr == cc ? 1.0 : 0.0;
-            } else {
-                const double* S = bufs.p[L.buf] + L.src_off;
-                v = L.trans ? S[(int64_t)cc * L.ld + rr] : S[(int64_t)rr * L.ld + cc];
+            for (int u = 0; u < 4; ++u) {
+                const int e = tid + 256 * u, rr = e & 31, cc = e >> 5;
+                T[cc][rr] = rr < tk.mt && cc < tk.nt ? S[(int64_t)(tk.c0 + cc) * L.ld + tk.r0 + rr] : 0.0;
             }
-            acc[u] += L.coef * v;
+            __syncthreads();
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int e = tid + 256 * u, r = e >> 5, c = e & 31;
+                acc[u] += L.coef * T[c][r];
+            }
+        } else {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int e = tid + 256 * u, r = e >> 5, c = e & 31;
+                if (r >= tk.mt || c >= tk.nt) continue;
+                const double v = L.ident ? (tk.r0 + r == tk.c0 + c ? 1.0 : 0.0)
+                                         : S[(int64_t)(tk.r0 + r) * L.ld + tk.c0 + c];
+                acc[u] += L.coef * v;
+            }
         }
     }
     double* D = bufs.p[tk.buf] + tk.dst_off;
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
-        if (r < tk.mt && c4 + u < tk.nt) D[(int64_t)(tk.r0 + r) * tk.ld + tk.c0 + c4 + u] = acc[u];
+    for (int u = 0; u < 4; ++u) {
+        const int e = tid + 256 * u, r = e >> 5, c = e & 31;
+        if (r < tk.mt && c < tk.nt) D[(int64_t)(tk.r0 + r) * tk.ld + tk.c0 + c] = acc[u];
+    }
 }
 
 int lincomb(Ctx* c, double* const* bufs, const LcTask* tasks, int ntasks, const LcTerm* terms) {
@@ -1255,27 +1279,37 @@ __global__ void __launch_bounds__(64) k_small_eigh(const double* __restrict__ G,
                 cs[t][1] = sn;
             }
             __syncthreads();
-            for (int e = t; e < (kk / 2) * k; e += 64) {
-                int pi = e / k, i = e % k;
-                int p = pr[pi][0], q = pr[pi][1];
-                if (q >= k) continue;
-                double c = cs[pi][0], sn = cs[pi][1];
-                double aip = A[i][p], aiq = A[i][q];
-                A[i][p] = c * aip - sn * aiq;
-                A[i][q] = sn * aip + c * aiq;
-                double vip = Vm[i][p], viq = Vm[i][q];
-                Vm[i][p] = c * vip - sn * viq;
-                Vm[i][q] = sn * vip + c * viq;
+            // lane t: pair t % 16, rows (or columns) t / 16 + 4 m
+            const int pi = t & 15, g = t >> 4;
+            if (pi < kk / 2 && pr[pi][1] < k) {
+                const int p = pr[pi][0], q = pr[pi][1];
+                const double c = cs[pi][0], sn = cs[pi][1];
+#pragma unroll
+                for (int m = 0; m < 8; ++m) {
+                    const int i = g + 4 * m;
+                    if (i < k) {
+                        const double aip = A[i][p], aiq = A[i][q];
+                        A[i][p] = c * aip - sn * aiq;
+                        A[i][q] = sn * aip + c * aiq;
+                        const double vip = Vm[i][p], viq = Vm[i][q];
+                        Vm[i][p] = c * vip - sn * viq;
+                        Vm[i][q] = sn * vip + c * viq;
+                    }
+                }
             }
             __syncthreads();
-            for (int e = t; e < (kk / 2) * k; e += 64) {
-                int pi = e / k, j = e % k;
-                int p = pr[pi][0], q = pr[pi][1];
-                if (q >= k) continue;
-                double c = cs[pi][0], sn = cs[pi][1];
-                double apj = A[p][j], aqj = A[q][j];
-                A[p][j] = c * apj - sn * aqj;
-                A[q][j] = sn * apj + c * aqj;
+            if (pi < kk / 2 && pr[pi][1] < k) {
+                const int p = pr[pi][0], q = pr[pi][1];
+                const double c = cs[pi][0], sn = cs[pi][1];
+#pragma unroll
+                for (int m = 0; m < 8; ++m) {
+                    const int j = g + 4 * m;
+                    if (j < k) {
+                        const double apj = A[p][j], aqj = A[q][j];
+                        A[p][j] = c * apj - sn * aqj;
+                        A[q][j] = sn * apj + c * aqj;
+                    }
+                }
             }
             __syncthreads();
         }
