@@ -404,10 +404,11 @@ def batched(k: int, precision: str = "fp32"):
     from workloads import batched_instances
     ws = batched_instances(k)
 
-    def make(w):
+    def make(w, group=1):
         h = w.hamiltonian()
         sp = h.space
-        c = pk.Context(precision=PREC[precision], davidson_tol=1e-7, noise=1e-4, noise_sweeps=1, seed=1507)
+        c = pk.Context(precision=PREC[precision], davidson_tol=1e-7, noise=1e-4, noise_sweeps=1, seed=1507,
+                       group_products=group)
         c.load_hamiltonian(sp.species, sp.two_m, h.eps, h.V.ravel(), h.n_p, h.n_n, h.two_M)
         return c
 
@@ -427,6 +428,16 @@ def batched(k: int, precision: str = "fp32"):
     t_con = time.perf_counter() - t
     for c in ctxs:
         c.close()
+    # the same call with every context launching its own products on its own stream
+    ctxs = [make(w, 0) for w in ws]
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    st_ind, out_ind = pk.sweep_many(ctxs, [w.D_schedule[0] for w in ws])
+    torch.cuda.synchronize()
+    t_ind = time.perf_counter() - t
+    for c in ctxs:
+        c.close()
+    diff_ind = max(abs(o["energy"] - e) / abs(e) for o, e in zip(out_ind, e_seq))
     diff = max(abs(o["energy"] - e) / abs(e) for o, e in zip(out, e_seq))
     flops = sum(o["heff_flops"] for o in out)
     # against the oracle's first-sweep energies of the instances it has
@@ -441,6 +452,7 @@ def batched(k: int, precision: str = "fp32"):
         pass
     res = {"batched": {"instances": k, "precision": precision, "status": st,
                        "sequential_s": t_seq, "concurrent_s": t_con, "speedup": t_seq / t_con,
+                       "independent_streams_s": t_ind, "independent_max_rel_energy_diff": diff_ind,
                        "heff_gflop_total": flops / 1e9, "heff_tflops_over_wall": flops / t_con / 1e12,
                        "max_rel_energy_diff": diff, "vs_oracle": vo,
                        "spaces": [w.space for w in ws], "D": [w.D_schedule[0] for w in ws]}}

@@ -90,6 +90,12 @@ typedef struct dmrg_options {
      * need several term groups, and products advanced by dmrg_sweep_many, are
      * launched directly.  0 (default): direct launches. */
     int32_t graph;
+    /* dmrg_sweep_many only: 1 (default) = when every context of the call has
+     * 1 and all are on one device, their H_eff products are launched in
+     * groups (one grouped persistent-GEMM launch per phase over all pending
+     * products); 0 = each context launches its own products on its own
+     * stream, and the device runs the contexts' kernels concurrently. */
+    int32_t group_products;
 } dmrg_options;
 
 typedef struct dmrg_sweep_stats {
@@ -261,9 +267,9 @@ dmrg_status dmrg_heff_configs(dmrg_ctx* ctx, uint64_t* configs);
 /* Advance n distinct contexts by one sweep each with their own ordering
  * (orderings[i] may be NULL) and D[i] (independent solves, e.g. many small
  * Hamiltonians).  Each context is driven by a host thread of its own (at most
- * 256 threads; further contexts wait for a free one).  When all contexts are
- * on one device their H_eff products are launched together by one launcher
- * thread: the products pending when it takes them (those that arrived while
+ * 16 threads; further contexts wait for a free one).  When all contexts are
+ * on one device and have group_products = 1, their H_eff products are
+ * launched together by one launcher thread: the products pending when it takes them (those that arrived while
  * the previous group was launched) form one grouped launch of the persistent
  * GEMM per product phase over all their plans, and one grouped split-K
  * reduction, on a stream of the call; each context's own work stays on its

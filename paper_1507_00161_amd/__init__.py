@@ -32,7 +32,8 @@ class Options(ctypes.Structure):
                 ("stream", ctypes.c_void_p), ("mem_cap_bytes", ctypes.c_uint64),
                 ("scratch_bytes", ctypes.c_uint64), ("trunc_eps", ctypes.c_double),
                 ("d_min", ctypes.c_int32), ("n_states", ctypes.c_int32),
-                ("measure", ctypes.c_int32), ("graph", ctypes.c_int32)]
+                ("measure", ctypes.c_int32), ("graph", ctypes.c_int32),
+                ("group_products", ctypes.c_int32)]
 
 
 class SweepStats(ctypes.Structure):

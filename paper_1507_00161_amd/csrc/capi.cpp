@@ -66,6 +66,7 @@ void dmrg_default_options(dmrg_options* o) {
     o->n_states = 1;
     o->measure = 0;
     o->graph = 0;
+    o->group_products = 1;
 }
 
 dmrg_status dmrg_create(const dmrg_options* opt, dmrg_ctx** out) {
@@ -77,7 +78,8 @@ dmrg_status dmrg_create(const dmrg_options* opt, dmrg_ctx** out) {
     if (o.precision < 0 || o.precision > 2 || o.davidson_tol <= 0 || o.davidson_max_iter < 1 ||
         o.davidson_max_subspace < 2 || o.davidson_max_subspace > 32 || o.noise < 0 || o.tie_tol < 0 ||
         !(o.trunc_eps >= 0) || o.d_min < 0 || o.n_states < 1 || o.n_states > 2 ||
-        (o.measure != 0 && o.measure != 1) || (o.graph != 0 && o.graph != 1)) {
+        (o.measure != 0 && o.measure != 1) || (o.graph != 0 && o.graph != 1) ||
+        (o.group_products != 0 && o.group_products != 1)) {
         g_create_err = "invalid option value";
         return DMRG_ERR_ARG;
     }
@@ -181,17 +183,21 @@ dmrg_status dmrg_sweep_many(dmrg_ctx** ctxs, int32_t n, const int32_t* const* or
         for (int32_t j = 0; j < i; ++j)
             if (ctxs[j] == ctxs[i]) return DMRG_ERR_ARG;   // a context runs on one thread at a time
     }
-    // Every context is driven by a host thread of its own (at most 256 at a
-    // time).  When all of them run on one device their H_eff products go
-    // through one batch: products pending together are launched as one
+    // Every context is driven by a host thread of its own (at most 16 at a
+    // time).  When all of them run on one device and ask for grouped
+    // products, their H_eff products go through one batch: products pending together are launched as one
     // grouped GEMM per phase over all their plans.  Each context's work keeps
     // its own order, so the results equal one-at-a-time sweeps.
     std::vector<dmrg_status> st(n, DMRG_OK);
     std::vector<dmrg_sweep_stats> res(n);
     std::atomic<int32_t> next(0);
-    const int nt = (int)std::min<int32_t>(n, 256);
+    // Host threads: the planning of a context is CPU work, so more threads
+    // than the host can run only add contention (and waiting threads spin
+    // in the HIP runtime's synchronisations).
+    const int nt = (int)std::min<int32_t>(n, 16);
     std::unique_ptr<dm::Batch> batch;
     bool same = n > 1;
+    for (int32_t i = 0; i < n && same; ++i) same = ctxs[i]->eng->options().group_products == 1;
     for (int32_t i = 1; i < n && same; ++i)
         same = dmrgdev::ctx_device(ctxs[i]->dev) == dmrgdev::ctx_device(ctxs[0]->dev);
     if (same) {

@@ -253,6 +253,7 @@ class Batch;  // products of several contexts launched together (batch.h)
 
 class Engine {
 public:
+    const dmrg_options& options() const { return opt_; }
     Engine(dmrgdev::Ctx* dev, const dmrg_options& opt) : dev_(dev), opt_(opt) {}
     ~Engine();
 

@@ -47,6 +47,7 @@ def test_default_options(lib):
     assert o.davidson_tol == 1e-7 and o.davidson_max_iter == 100 and o.davidson_max_subspace == 24
     assert o.tie_tol == 1e-13 and o.noise == 0.0 and o.select_basis == 0
     assert o.trunc_eps == 0.0 and o.d_min == 0 and o.n_states == 1 and o.measure == 0 and o.graph == 0
+    assert o.group_products == 1
 
 
 def test_status_strings(lib):
@@ -65,7 +66,8 @@ def test_bad_options_rejected_before_any_device_call(lib):
     assert lib.dmrg_create(ctypes.byref(o), ctypes.byref(h)) == -1
     assert h.value is None
     for field, value in (("trunc_eps", -1e-6), ("d_min", -1), ("n_states", 0), ("n_states", 3),
-                         ("measure", 2), ("measure", -1)):
+                         ("measure", 2), ("measure", -1), ("graph", 2), ("group_products", 2),
+                         ("group_products", -1)):
         lib.dmrg_default_options(ctypes.byref(o))
         setattr(o, field, value)
         assert lib.dmrg_create(ctypes.byref(o), ctypes.byref(h)) == -1, field

@@ -495,11 +495,12 @@ def test_entropies_full_size_pf_8p8n_D2048(pk):
         assert (np.abs(hop) <= 0.5 + 1e-12).all()   # |<c+_i c_j>| <= sqrt(<n_i><1 - n_j>)-type bound
 
 
-@pytest.mark.parametrize("precision,rtol", [(0, 1e-8), (1, 1e-6)])
-def test_sweep_many_matches_oracle_batched(pk, precision, rtol):
+@pytest.mark.parametrize("precision,rtol,group", [(0, 1e-8, 1), (1, 1e-6, 1), (1, 1e-6, 0)])
+def test_sweep_many_matches_oracle_batched(pk, precision, rtol, group):
     """The independent small solves of the batched workload (seeded p, sd and
     pf instances, 2..8 particles per species, D from 64 to 512), advanced
-    together by dmrg_sweep_many with their products launched in groups: the
+    together by dmrg_sweep_many with their products launched in groups
+    (group_products = 1) or each context on its own stream (0): the
     first-sweep energy of every instance the oracle has
     (tests/golden/oracle_batched.json: p and sd at every D, pf at D <= 128)."""
     from workloads import batched_instances
@@ -509,7 +510,7 @@ def test_sweep_many_matches_oracle_batched(pk, precision, rtol):
     ws = batched_instances(g["count"])
     idx = sorted(int(i) for i in g["instances"])
     assert len(idx) >= 20
-    ctxs = [_ctx(pk, ws[i].hamiltonian(), precision=precision, **g["options"]) for i in idx]
+    ctxs = [_ctx(pk, ws[i].hamiltonian(), precision=precision, group_products=group, **g["options"]) for i in idx]
     st, out = pk.sweep_many(ctxs, [ws[i].D_schedule[0] for i in idx])
     assert st in (0, 1)
     for i, o in zip(idx, out):
