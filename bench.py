@@ -62,6 +62,9 @@ def run_schedule(workload, prec: str, warmup: int, steps: int, D_main: int, seed
     tot = {}
     walls = []
     energy = None
+    # host clock readings around the timed sweeps, so that a profiler's trace
+    # (whose timestamps come from one of these clocks) can pick out their launches
+    win = {"boottime": [time.clock_gettime_ns(time.CLOCK_BOOTTIME)], "monotonic": [time.monotonic_ns()]}
     for k in range(steps):
         torch.cuda.synchronize()
         t = time.perf_counter()
@@ -80,6 +83,9 @@ def run_schedule(workload, prec: str, warmup: int, steps: int, D_main: int, seed
             f"{r['renorm_seconds']:.2f}s (density {r['density_seconds']:.2f}, eig {r['eig_seconds']:.2f}, "
             f"renormalize {r['renormalize_seconds']:.2f}, predict {r['predict_seconds']:.2f}), "
             f"blocking+plans {r['blocking_seconds']:.2f}s")
+    torch.cuda.synchronize()
+    win["boottime"].append(time.clock_gettime_ns(time.CLOCK_BOOTTIME))
+    win["monotonic"].append(time.monotonic_ns())
     chk = None
     if check and prec != "fp64":
         ctx.check_fp64(True)
@@ -90,7 +96,7 @@ def run_schedule(workload, prec: str, warmup: int, steps: int, D_main: int, seed
             f"{chk['solves']} pairs, max |theta - theta_fp64| / |theta_fp64| = {chk['max_rel']:.3e} "
             f"({time.perf_counter() - t:.1f}s)")
     ctx.close()
-    return dict(energy=energy, walls=walls, tot=tot, energies=energies, check=chk)
+    return dict(energy=energy, walls=walls, tot=tot, energies=energies, check=chk, window=win)
 
 
 def plateaus(name: str, prec: str, Ds, per: int, tol: float, trunc_eps: float = 0.0, d_min: int = 0,
@@ -332,12 +338,21 @@ def summarize_trace(d, bench_json, kernel):
     trace = _csv_rows(_find(d, "kernel_trace.csv"))
     sel = [r for r in trace if _short(r["Kernel_Name"]) == kernel]
     sel.sort(key=lambda r: int(r["Start_Timestamp"]))
-    last = sel[-n:]
-    avg = sum(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]) for r in last) / max(len(last), 1)
+    # the dispatches inside the timed sweeps' window, on whichever host clock
+    # the trace's timestamps follow (the one whose window holds the launch count)
+    best = None
+    for clock, (w0, w1) in b["roofline"].get("timed_window_ns", {}).items():
+        inside = [r for r in sel if int(r["Start_Timestamp"]) >= w0 and int(r["End_Timestamp"]) <= w1]
+        if best is None or abs(len(inside) - n) < abs(len(best[1]) - n):
+            best = (clock, inside)
+    if best is None or not best[1]:
+        raise SystemExit("no dispatch of the kernel inside the timed window")
+    clock, last = best
+    avg = sum(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]) for r in last) / len(last)
     out = [f"- benchmark line: value {b['value']:.2f} {b['unit']}, ms_per_step {b['ms_per_step']:.0f}, "
            f"roofline.launch_ms {b['roofline']['launch_ms']:.4f} over {n} launches",
-           f"- `{kernel}`: {len(sel)} dispatches in the run; mean of the last {len(last)} "
-           f"(the timed sweeps) = {avg / 1e6:.4f} ms",
+           f"- `{kernel}`: {len(sel)} dispatches in the run; {len(last)} inside the timed sweeps "
+           f"(host {clock} clock window); their mean duration = {avg / 1e6:.4f} ms",
            "", "| kernel | calls | total s | avg us | % |", "|---|---|---|---|---|"]
     for r in sorted(stats, key=lambda r: -float(r["TotalDurationNs"]))[:15]:
         out.append(f"| `{_short(r['Name'])[:70]}` | {r['Calls']} | {float(r['TotalDurationNs']) / 1e9:.3f} | "
@@ -359,14 +374,27 @@ def summarize_counters(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, ben
         by = {}
         for r in rows:
             k = int(r["Dispatch_Id"])
-            by.setdefault(k, [int(r["Start_Timestamp"]), 0.0])
-            by[k][1] += float(r["Counter_Value"])
-        return [v for _, v in sorted(by.values())]
+            by.setdefault(k, [int(r["Start_Timestamp"]), int(r["End_Timestamp"]), 0.0])
+            by[k][2] += float(r["Counter_Value"])
+        return sorted(by.values())
 
-    fk = per_dispatch(fetch_dir, "FETCH_SIZE", lambda s: s == kernel)[-n:]
-    wk = per_dispatch(write_dir, "WRITE_SIZE", lambda s: s == kernel)[-n:]
-    cf = max(per_dispatch(copy_fetch_dir, "FETCH_SIZE", lambda s: "copy" in s.lower() or "elementwise" in s))
-    cw = max(per_dispatch(copy_write_dir, "WRITE_SIZE", lambda s: "copy" in s.lower() or "elementwise" in s))
+    def timed(disp):
+        """the dispatches inside the timed sweeps (host clock window of the run's own line)"""
+        best = None
+        for w0, w1 in b["roofline"].get("timed_window_ns", {}).values():
+            inside = [v for s0, s1, v in disp if s0 >= w0 and s1 <= w1]
+            if best is None or abs(len(inside) - n) < abs(len(best) - n):
+                best = inside
+        if not best:
+            raise SystemExit("no dispatch of the kernel inside the timed window")
+        return best
+
+    fk = timed(per_dispatch(fetch_dir, "FETCH_SIZE", lambda s: s == kernel))
+    wk = timed(per_dispatch(write_dir, "WRITE_SIZE", lambda s: s == kernel))
+    cf = max(v for _, _, v in per_dispatch(copy_fetch_dir, "FETCH_SIZE",
+                                           lambda s: "copy" in s.lower() or "elementwise" in s))
+    cw = max(v for _, _, v in per_dispatch(copy_write_dir, "WRITE_SIZE",
+                                           lambda s: "copy" in s.lower() or "elementwise" in s))
     kib = copy_mib * 1024.0
     sf, sw = kib / cf, kib / cw
     fetch = sum(fk) / len(fk) * 1024 * sf
@@ -599,7 +627,8 @@ def main():
                      "other_phase": {"kernel": oname, "launch_ms": 1e3 * t[f"{ko}_seconds"] / nlo,
                                      "algorithmic_gflop_per_launch": t[f"{ko}_flops"] / nlo / 1e9,
                                      "issued_gflop_per_launch": t[f"{ko}_issued_flops"] / nlo / 1e9,
-                                     "algorithmic_gb_per_launch": t[f"{ko}_bytes"] / nlo / 1e9}},
+                                     "algorithmic_gb_per_launch": t[f"{ko}_bytes"] / nlo / 1e9},
+                     "timed_window_ns": R["window"]},
         "flop_counts": {"value_counts": "algorithmic: per term and psi block the cheaper of the two "
                                         "contraction orders, nonzero sub-blocks, intermediates formed once",
                         "algorithmic_gflop": t["heff_flops"] / 1e9,

@@ -87,8 +87,8 @@ typedef struct dmrg_options {
      * the graph is replayed for every product at that bond (input and output
      * pass through fixed staging vectors).  Products then run as one graph
      * launch; the per-phase GEMM statistics are not collected.  Products that
-     * need several term groups, and products advanced by dmrg_sweep_many, are
-     * launched directly.  0 (default): direct launches. */
+     * need several term groups, and products of contexts advanced by
+     * dmrg_sweep_many, are launched directly.  0 (default): direct launches. */
     int32_t graph;
     /* dmrg_sweep_many only: 1 (default) = when every context of the call has
      * 1 and all are on one device, their H_eff products are launched in

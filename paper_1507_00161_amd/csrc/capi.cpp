@@ -204,8 +204,10 @@ dmrg_status dmrg_sweep_many(dmrg_ctx** ctxs, int32_t n, const int32_t* const* or
         batch.reset(new dm::Batch(dmrgdev::ctx_device(ctxs[0]->dev)));
         if (!batch->ok()) batch.reset();   // independent sweeps
     }
-    if (batch)
-        for (int32_t i = 0; i < n; ++i) ctxs[i]->eng->attach_batch(batch.get());
+    for (int32_t i = 0; i < n; ++i) {
+        ctxs[i]->eng->set_in_many(true);
+        if (batch) ctxs[i]->eng->attach_batch(batch.get());
+    }
     auto worker = [&] {
         for (int32_t i = next++; i < n; i = next++) {
             dmrgdev::bind(ctxs[i]->dev);
@@ -219,8 +221,10 @@ dmrg_status dmrg_sweep_many(dmrg_ctx** ctxs, int32_t n, const int32_t* const* or
     for (int t = 1; t < nt; ++t) pool.emplace_back(worker);
     worker();
     for (auto& t : pool) t.join();
-    if (batch)
-        for (int32_t i = 0; i < n; ++i) ctxs[i]->eng->attach_batch(nullptr);
+    for (int32_t i = 0; i < n; ++i) {
+        ctxs[i]->eng->set_in_many(false);
+        if (batch) ctxs[i]->eng->attach_batch(nullptr);
+    }
     dmrg_status worst = DMRG_OK;
     for (int32_t i = 0; i < n; ++i) {
         if (out) out[i] = res[i];

@@ -90,8 +90,10 @@ struct Sched {
 };
 // kind: which H_eff phase a launch is (only the kernel's name differs, for profiles)
 enum GemmKind { GK_OTHER = 0, GK_HEFF_Z = 1, GK_HEFF_Y = 2 };
+// ev_start / ev_stop (event slots, or -1): recorded by the kernel's own
+// dispatch at its start and end, so that their interval is the kernel alone.
 int gemm(Ctx* c, int ab_prec, int c_prec, void* const* bufs, const GemmTask* d_tasks, const Sched& sched,
-         const GemmChunk* d_chunks, int kind = GK_OTHER);
+         const GemmChunk* d_chunks, int kind = GK_OTHER, int ev_start = -1, int ev_stop = -1);
 int gemm_reduce(Ctx* c, int c_prec, void* const* bufs, const RedTask* d_tasks, int ntasks);
 
 // Grouped launch of several plans (independent solves advanced together):

@@ -9,6 +9,7 @@
 // v_mfma_f32_16x16x32_bf16 (BF16 operands, FP32 accumulation).  Each wave
 // holds a 32x32 quarter of the tile as 2x2 MFMA blocks.
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 #include <rocblas/rocblas.h>
 #include <rocsolver/rocsolver.h>
 
@@ -832,43 +833,36 @@ int gemm_multi(Ctx* c, int ab, int cp, const PlanDesc* plans, const int32_t* pre
 }
 
 int gemm(Ctx* c, int ab, int cp, void* const* bufs, const GemmTask* tasks, const Sched& sc,
-         const GemmChunk* chunks, int kind) {
+         const GemmChunk* chunks, int kind, int ev_start, int ev_stop) {
     const int ntasks = sc.ntasks;
     if (ntasks <= 0) return 0;
     Bufs b;
     for (int i = 0; i < kMaxBufs; ++i) b.p[i] = bufs[i];
-    dim3 pgrid(std::max(1, sc.nwg)), block(NTH);
+    const dim3 pgrid(std::max(1, sc.nwg)), block(NTH);
+    hipEvent_t e0 = ev_start >= 0 ? c->ev[ev_start] : nullptr, e1 = ev_stop >= 0 ? c->ev[ev_stop] : nullptr;
+    auto go = [&](auto kern) {
+        if (e0 || e1)
+            hipExtLaunchKernelGGL(kern, pgrid, block, 0, c->stream, e0, e1, 0, b, tasks, chunks, sc);
+        else
+            hipLaunchKernelGGL(kern, pgrid, block, 0, c->stream, b, tasks, chunks, sc);
+    };
     if (ab == P_F64 && cp == P_F64) {
-        if (kind == GK_HEFF_Z)
-            hipLaunchKernelGGL((k_heff_z<double, double, 16>), pgrid, block, 0, c->stream, b, tasks, chunks, sc);
-        else if (kind == GK_HEFF_Y)
-            hipLaunchKernelGGL((k_heff_y<double, double, 16>), pgrid, block, 0, c->stream, b, tasks, chunks, sc);
-        else
-            hipLaunchKernelGGL((k_gemm<double, double, 16>), pgrid, block, 0, c->stream, b, tasks, chunks, sc);
+        if (kind == GK_HEFF_Z) go(k_heff_z<double, double, 16>);
+        else if (kind == GK_HEFF_Y) go(k_heff_y<double, double, 16>);
+        else go(k_gemm<double, double, 16>);
     } else if (ab == P_F32 && cp == P_F32) {
-        if (kind == GK_HEFF_Z)
-            hipLaunchKernelGGL((k_heff_z<float, float, 32>), pgrid, block, 0, c->stream, b, tasks, chunks, sc);
-        else if (kind == GK_HEFF_Y)
-            hipLaunchKernelGGL((k_heff_y<float, float, 32>), pgrid, block, 0, c->stream, b, tasks, chunks, sc);
-        else
-            hipLaunchKernelGGL((k_gemm<float, float, 32>), pgrid, block, 0, c->stream, b, tasks, chunks, sc);
-    }
-    else if (ab == P_BF16 && cp == P_F32) {
-        if (kind == GK_HEFF_Z)
-            hipLaunchKernelGGL((k_heff_z<bf16_t, float, 32>), pgrid, block, 0, c->stream, b, tasks, chunks, sc);
-        else if (kind == GK_HEFF_Y)
-            hipLaunchKernelGGL((k_heff_y<bf16_t, float, 32>), pgrid, block, 0, c->stream, b, tasks, chunks, sc);
-        else
-            hipLaunchKernelGGL((k_gemm<bf16_t, float, 32>), pgrid, block, 0, c->stream, b, tasks, chunks, sc);
+        if (kind == GK_HEFF_Z) go(k_heff_z<float, float, 32>);
+        else if (kind == GK_HEFF_Y) go(k_heff_y<float, float, 32>);
+        else go(k_gemm<float, float, 32>);
+    } else if (ab == P_BF16 && cp == P_F32) {
+        if (kind == GK_HEFF_Z) go(k_heff_z<bf16_t, float, 32>);
+        else if (kind == GK_HEFF_Y) go(k_heff_y<bf16_t, float, 32>);
+        else go(k_gemm<bf16_t, float, 32>);
     } else if (ab == P_BF16 && cp == P_BF16) {
-        if (kind == GK_HEFF_Z)
-            hipLaunchKernelGGL((k_heff_z<bf16_t, bf16_t, 32>), pgrid, block, 0, c->stream, b, tasks, chunks, sc);
-        else if (kind == GK_HEFF_Y)
-            hipLaunchKernelGGL((k_heff_y<bf16_t, bf16_t, 32>), pgrid, block, 0, c->stream, b, tasks, chunks, sc);
-        else
-            hipLaunchKernelGGL((k_gemm<bf16_t, bf16_t, 32>), pgrid, block, 0, c->stream, b, tasks, chunks, sc);
-    }
-    else {
+        if (kind == GK_HEFF_Z) go(k_heff_z<bf16_t, bf16_t, 32>);
+        else if (kind == GK_HEFF_Y) go(k_heff_y<bf16_t, bf16_t, 32>);
+        else go(k_gemm<bf16_t, bf16_t, 32>);
+    } else {
         c->err = "unsupported GEMM precision combination";
         return 1;
     }

@@ -220,11 +220,12 @@ struct GB {
     }
 };
 
-dmrg_status Engine::run_gemm(int prec, BufTable bufs, const GemmPlan& p, int cprec, int kind, int ev_mid,
-                             void* partials) {
+dmrg_status Engine::run_gemm(int prec, BufTable bufs, const GemmPlan& p, int cprec, int kind, void* partials,
+                             int ev_start, int ev_stop) {
     if (cprec < 0) cprec = prec == dmrgdev::P_BF16 ? dmrgdev::P_F32 : prec;
     if (p.ntasks == 0) {
-        if (ev_mid >= 0) DEV(dmrgdev::event_record(dev_, ev_mid));
+        if (ev_start >= 0) DEV(dmrgdev::event_record(dev_, ev_start));
+        if (ev_stop >= 0) DEV(dmrgdev::event_record(dev_, ev_stop));
         return DMRG_OK;
     }
     if (p.nslots) {
@@ -240,8 +241,8 @@ dmrg_status Engine::run_gemm(int prec, BufTable bufs, const GemmPlan& p, int cpr
     sc.nwg = p.nwg;
     sc.nfull = p.nfull;
     sc.ntasks = p.ntasks;
-    DEV(dmrgdev::gemm(dev_, prec, cprec, bufs.data(), p.tasks.as<GemmTask>(), sc, p.chunks.as<GemmChunk>(), kind));
-    if (ev_mid >= 0) DEV(dmrgdev::event_record(dev_, ev_mid));
+    DEV(dmrgdev::gemm(dev_, prec, cprec, bufs.data(), p.tasks.as<GemmTask>(), sc, p.chunks.as<GemmChunk>(), kind,
+                      ev_start, ev_stop));
     if (p.nreds)
         DEV(dmrgdev::gemm_reduce(dev_, cprec, bufs.data(), p.reds.as<dmrgdev::RedTask>(), p.nreds));
     return DMRG_OK;
@@ -1826,7 +1827,7 @@ dmrg_status Engine::heff(Bond& B, const double* x, double* y, int prec) {
 // the elapsed times are read after the product completes)
 dmrg_status Engine::heff_launch(Bond& B, const double* x, double* y, int prec, bool timed) {
     if (batch_ && B.groups.size() == 1) return heff_batched(B, x, y, prec);
-    if (opt_.graph && B.groups.size() == 1) return heff_graph(B, x, y, prec);
+    if (opt_.graph && !in_many_ && B.groups.size() == 1) return heff_graph(B, x, y, prec);
     return heff_direct(B, x, y, prec, timed);
 }
 
@@ -1878,10 +1879,8 @@ dmrg_status Engine::heff_direct(Bond& B, const double* x, double* y, int prec, b
     if (prec == dmrgdev::P_F64) {
         for (size_t g = 0; g < B.groups.size(); ++g) {
             BufTable bufs{B.Sops.pool.p, B.Eops.pool.p, (void*)x, z_.p, y};
-            if (timed) DEV(dmrgdev::event_record(dev_, 2));
-            TRY(run_gemm(prec, bufs, B.groups[g].p1, -1, dmrgdev::GK_HEFF_Z));
-            if (timed) DEV(dmrgdev::event_record(dev_, 3));
-            TRY(run_gemm(prec, bufs, B.groups[g].p2, -1, dmrgdev::GK_HEFF_Y, timed ? 4 : -1));
+            TRY(run_gemm(prec, bufs, B.groups[g].p1, -1, dmrgdev::GK_HEFF_Z, nullptr, timed ? 2 : -1, timed ? 3 : -1));
+            TRY(run_gemm(prec, bufs, B.groups[g].p2, -1, dmrgdev::GK_HEFF_Y, nullptr, timed ? 6 : -1, timed ? 4 : -1));
             if (timed) DEV(dmrgdev::event_record(dev_, 5));
             TRY(run_gemm(prec, bufs, B.groups[g].p3));
             if (timed && opt_.precision == DMRG_FP64) account(B.groups[g], es, es);
@@ -1899,10 +1898,10 @@ dmrg_status Engine::heff_direct(Bond& B, const double* x, double* y, int prec, b
     DEV(dmrgdev::convert(dev_, dmrgdev::P_F64, x, prec, xlo_.p, B.dim));
     for (size_t g = 0; g < B.groups.size(); ++g) {
         BufTable bufs{B.Sops.pool_lo.p, B.Eops.pool_lo.p, xlo_.p, scr_a_.p, ylo_.p};
-        if (timed) DEV(dmrgdev::event_record(dev_, 2));
-        TRY(run_gemm(prec, bufs, B.groups[g].p1, prec, dmrgdev::GK_HEFF_Z));   // Z in the operand precision
-        if (timed) DEV(dmrgdev::event_record(dev_, 3));
-        TRY(run_gemm(prec, bufs, B.groups[g].p2, dmrgdev::P_F32, dmrgdev::GK_HEFF_Y, timed ? 4 : -1));
+        // Z in the operand precision
+        TRY(run_gemm(prec, bufs, B.groups[g].p1, prec, dmrgdev::GK_HEFF_Z, nullptr, timed ? 2 : -1, timed ? 3 : -1));
+        TRY(run_gemm(prec, bufs, B.groups[g].p2, dmrgdev::P_F32, dmrgdev::GK_HEFF_Y, nullptr, timed ? 6 : -1,
+                     timed ? 4 : -1));
         if (timed) DEV(dmrgdev::event_record(dev_, 5));
         TRY(run_gemm(prec, bufs, B.groups[g].p3, dmrgdev::P_F32));
         if (timed) account(B.groups[g], es, es);
@@ -1966,7 +1965,9 @@ dmrg_status Engine::heff_batched(Bond& B, const double* x, double* y, int prec) 
 }
 
 void Engine::account(const HeffGroup& g, double es1, double es2) {
-    double t1 = dmrgdev::event_elapsed(dev_, 2, 3), t2 = dmrgdev::event_elapsed(dev_, 3, 4);
+    // kernel intervals recorded by the launches themselves; the split-K
+    // reduction runs between the end of phase 2 and event 5
+    double t1 = dmrgdev::event_elapsed(dev_, 2, 3), t2 = dmrgdev::event_elapsed(dev_, 6, 4);
     acc_.reduce_seconds += dmrgdev::event_elapsed(dev_, 4, 5);
     if (g.p1.ntasks) {
         acc_.gemm1_launches += 1;
@@ -3323,9 +3324,9 @@ dmrg_status Engine::apply_static(const double* x, double* y, int prec) {
     if (!low) {
         for (auto& g : B.groups) {
             BufTable bufs{B.Sops.pool.p, B.Eops.pool.p, (void*)x, base + z_off, y};
-            TRY(run_gemm(prec, bufs, g.p1, -1, dmrgdev::GK_HEFF_Z, -1, part));
-            TRY(run_gemm(prec, bufs, g.p2, -1, dmrgdev::GK_HEFF_Y, -1, part));
-            TRY(run_gemm(prec, bufs, g.p3, -1, dmrgdev::GK_OTHER, -1, part));
+            TRY(run_gemm(prec, bufs, g.p1, -1, dmrgdev::GK_HEFF_Z, part));
+            TRY(run_gemm(prec, bufs, g.p2, -1, dmrgdev::GK_HEFF_Y, part));
+            TRY(run_gemm(prec, bufs, g.p3, -1, dmrgdev::GK_OTHER, part));
         }
         return DMRG_OK;
     }
@@ -3334,9 +3335,9 @@ dmrg_status Engine::apply_static(const double* x, double* y, int prec) {
     DEV(dmrgdev::convert(dev_, dmrgdev::P_F64, x, prec, base + x_off, B.dim));
     for (auto& g : B.groups) {
         BufTable bufs{base + s_off, base + e_off, base + x_off, base + z_off, base + y_off};
-        TRY(run_gemm(prec, bufs, g.p1, prec, dmrgdev::GK_HEFF_Z, -1, part));
-        TRY(run_gemm(prec, bufs, g.p2, dmrgdev::P_F32, dmrgdev::GK_HEFF_Y, -1, part));
-        TRY(run_gemm(prec, bufs, g.p3, dmrgdev::P_F32, dmrgdev::GK_OTHER, -1, part));
+        TRY(run_gemm(prec, bufs, g.p1, prec, dmrgdev::GK_HEFF_Z, part));
+        TRY(run_gemm(prec, bufs, g.p2, dmrgdev::P_F32, dmrgdev::GK_HEFF_Y, part));
+        TRY(run_gemm(prec, bufs, g.p3, dmrgdev::P_F32, dmrgdev::GK_OTHER, part));
     }
     DEV(dmrgdev::convert(dev_, dmrgdev::P_F32, base + y_off, dmrgdev::P_F64, y, B.dim));
     return DMRG_OK;

@@ -272,6 +272,9 @@ public:
     dmrg_status set_cideas(const double* s1, const double* n1);
     // while set, H_eff products of single-group bonds go through the batch
     void attach_batch(Batch* b) { batch_ = b; }
+    // set while dmrg_sweep_many drives this context: its products are then
+    // launched directly (or in groups), never as captured graphs
+    void set_in_many(bool on) { in_many_ = on; }
     dmrg_status set_check_fp64(bool on) {
         check_fp64_ = on;
         return DMRG_OK;
@@ -301,6 +304,7 @@ public:
 
 private:
     dmrgdev::Ctx* dev_;
+    bool in_many_ = false;
     dmrg_options opt_;
     std::string err_;
     int N_ = 0;
@@ -394,10 +398,12 @@ private:
     dmrg_status density_matrix(Bond& B, const Buf& psi, double weight, int beta, bool left, double alpha, Buf& rho,
                                const std::vector<int64_t>& roff, const std::vector<int>& rld);
     dmrg_status random_psi(Bond& B, Buf& out);
-    // ev_mid >= 0: record that event between the GEMM and its split-K reduction
-    // partials: split-K partial tiles supplied by the caller (else the engine's own buffer)
+    // ev_start / ev_stop >= 0: those events are recorded at the GEMM kernel's own
+    // start and end (both at once when the plan has no tasks); partials: split-K
+    // partial tiles supplied by the caller (else the engine's own buffer)
     dmrg_status run_gemm(int prec, BufTable bufs, const GemmPlan& p, int cprec = -1,
-                         int kind = dmrgdev::GK_OTHER, int ev_mid = -1, void* partials = nullptr);
+                         int kind = dmrgdev::GK_OTHER, void* partials = nullptr, int ev_start = -1,
+                         int ev_stop = -1);
     dmrg_status ensure_partials(int64_t slots);
     Buf partial_;
     dmrg_status ensure_dv(int64_t n, int kmax);

@@ -495,8 +495,12 @@ def test_entropies_full_size_pf_8p8n_D2048(pk):
         assert (np.abs(hop) <= 0.5 + 1e-12).all()   # |<c+_i c_j>| <= sqrt(<n_i><1 - n_j>)-type bound
 
 
-@pytest.mark.parametrize("precision,rtol,group", [(0, 1e-8, 1), (1, 1e-6, 1), (1, 1e-6, 0)])
-def test_sweep_many_matches_oracle_batched(pk, precision, rtol, group):
+@pytest.mark.parametrize("precision,rtol,group,graph", [
+    (0, 1e-8, 1, 0), (1, 1e-6, 1, 0), (1, 1e-6, 0, 0),
+    pytest.param(1, 1e-6, 0, 1, marks=pytest.mark.skip(
+        reason="captured-graph products in concurrent contexts ended the process with a host segmentation "
+               "fault (cause not found); dmrg_sweep_many now launches every product directly"))])
+def test_sweep_many_matches_oracle_batched(pk, precision, rtol, group, graph):
     """The independent small solves of the batched workload (seeded p, sd and
     pf instances, 2..8 particles per species, D from 64 to 512), advanced
     together by dmrg_sweep_many with their products launched in groups
@@ -510,7 +514,8 @@ def test_sweep_many_matches_oracle_batched(pk, precision, rtol, group):
     ws = batched_instances(g["count"])
     idx = sorted(int(i) for i in g["instances"])
     assert len(idx) >= 20
-    ctxs = [_ctx(pk, ws[i].hamiltonian(), precision=precision, group_products=group, **g["options"]) for i in idx]
+    ctxs = [_ctx(pk, ws[i].hamiltonian(), precision=precision, group_products=group, graph=graph, **g["options"])
+            for i in idx]
     st, out = pk.sweep_many(ctxs, [ws[i].D_schedule[0] for i in idx])
     assert st in (0, 1)
     for i, o in zip(idx, out):
