@@ -349,10 +349,24 @@ def summarize_trace(d, bench_json, kernel):
         raise SystemExit("no dispatch of the kernel inside the timed window")
     clock, last = best
     avg = sum(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]) for r in last) / len(last)
+    # device busy time in the window: the union of all kernels' intervals
+    w0, w1 = b["roofline"]["timed_window_ns"][clock]
+    iv = sorted((int(r["Start_Timestamp"]), int(r["End_Timestamp"])) for r in trace
+                if int(r["Start_Timestamp"]) >= w0 and int(r["End_Timestamp"]) <= w1)
+    busy, cs, ce = 0, None, None
+    for s0, s1 in iv:
+        if ce is None or s0 > ce:
+            busy += (ce - cs) if ce is not None else 0
+            cs, ce = s0, s1
+        else:
+            ce = max(ce, s1)
+    busy += (ce - cs) if ce is not None else 0
     out = [f"- benchmark line: value {b['value']:.2f} {b['unit']}, ms_per_step {b['ms_per_step']:.0f}, "
            f"roofline.launch_ms {b['roofline']['launch_ms']:.4f} over {n} launches",
            f"- `{kernel}`: {len(sel)} dispatches in the run; {len(last)} inside the timed sweeps "
            f"(host {clock} clock window); their mean duration = {avg / 1e6:.4f} ms",
+           f"- device busy inside the timed window (union of all kernel intervals): {busy / 1e9:.2f} s of "
+           f"{(w1 - w0) / 1e9:.2f} s",
            "", "| kernel | calls | total s | avg us | % |", "|---|---|---|---|---|"]
     for r in sorted(stats, key=lambda r: -float(r["TotalDurationNs"]))[:15]:
         out.append(f"| `{_short(r['Name'])[:70]}` | {r['Calls']} | {float(r['TotalDurationNs']) / 1e9:.3f} | "
@@ -386,7 +400,10 @@ def summarize_counters(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, ben
             if best is None or abs(len(inside) - n) < abs(len(best) - n):
                 best = inside
         if not best:
-            raise SystemExit("no dispatch of the kernel inside the timed window")
+            # counter collection stamps dispatches on another clock: the run has
+            # no check sweep and no CPU baseline (--no-check --no-cpu-baseline),
+            # so the timed sweeps' launches are the kernel's last n
+            return [v for _, _, v in disp[-n:]]
         return best
 
     fk = timed(per_dispatch(fetch_dir, "FETCH_SIZE", lambda s: s == kernel))

@@ -16,6 +16,7 @@
 #include "batch.h"
 
 #include <algorithm>
+#include <atomic>
 #include <cstdio>
 #include <chrono>
 #include <cmath>
@@ -266,7 +267,7 @@ dmrg_status Engine::ensure_partials(int64_t slots) {
 // (pure clears) are moved behind all others.  The task vector is reordered in place: work-group
 // w = 8 j + x runs [wg_off[w], wg_off[w+1]).
 static void schedule_tasks(const GB& g, std::vector<GemmTask>& tasks, const std::vector<int32_t>& owner,
-                           std::vector<int32_t>& wg_off, int& nwg, int& nfull) {
+                           std::vector<int32_t>& wg_off, int& nwg, int& nfull, bool parallel) {
     const int64_t n = (int64_t)tasks.size();
     std::vector<float> cost(n, 0.f);
     double total = 0.0;
@@ -341,13 +342,13 @@ static void schedule_tasks(const GB& g, std::vector<GemmTask>& tasks, const std:
     // loads still end within about one task of each other.
     std::vector<int32_t> wg_of(n, -1);
     typedef std::pair<double, int> QE;
-    std::vector<QE> heap;
     auto cmp = [](const QE& a, const QE& b) { return a > b; };   // min-heap on (load, j)
-    for (int x = 0; x < 8; ++x) {
+    // the XCDs' dealings touch disjoint tasks: one host thread each for large plans
+    auto deal = [&](int x) {
+        std::vector<QE> heap;
         auto b = order.begin() + xoff[x], e = order.begin() + xoff[x + 1];
         if (lpt)
             std::sort(b, e, [&](int64_t p, int64_t q) { return cost[p] != cost[q] ? cost[p] > cost[q] : p < q; });
-        heap.clear();
         for (int j = 0; j < gw; ++j) heap.push_back({0.0, j});
         std::make_heap(heap.begin(), heap.end(), cmp);
         for (auto it = b; it != e; ++it) {
@@ -357,6 +358,14 @@ static void schedule_tasks(const GB& g, std::vector<GemmTask>& tasks, const std:
             q.first += cost[*it];
             std::push_heap(heap.begin(), heap.end(), cmp);
         }
+    };
+    if (parallel && nf >= 8192) {
+        std::vector<std::thread> th;
+        for (int x = 1; x < 8; ++x) th.emplace_back(deal, x);
+        deal(0);
+        for (auto& t : th) t.join();
+    } else {
+        for (int x = 0; x < 8; ++x) deal(x);
     }
     // counting sort by work-group; within a work-group, tasks keep dealing order
     wg_off.assign(nwg + 1, 0);
@@ -379,7 +388,7 @@ struct PlanHost {
     std::vector<dmrgdev::RedTask> reds;
     std::vector<int32_t> wg_off;
 };
-static void plan_host(const GB& g, GemmPlan& p, PlanHost& h) {
+static void plan_host(const GB& g, GemmPlan& p, PlanHost& h, bool parallel = true) {
     using dmrgdev::kTileM;
     using dmrgdev::kTileN;
     std::vector<GemmTask>& tasks = h.tasks;
@@ -483,7 +492,7 @@ static void plan_host(const GB& g, GemmPlan& p, PlanHost& h) {
         slot += (int64_t)tiles.size() * nparts;
     }
     (void)ntiles;
-    schedule_tasks(g, tasks, owner, h.wg_off, p.nwg, p.nfull);
+    schedule_tasks(g, tasks, owner, h.wg_off, p.nwg, p.nfull, parallel);
     p.ntasks = (int)tasks.size();
     p.nreds = (int)reds.size();
     p.nslots = slot;
@@ -505,15 +514,16 @@ static dmrg_status plan_upload(Engine& e, const GB& g, GemmPlan& p, const PlanHo
 
 static dmrg_status finish_plan(Engine& e, GB& g, GemmPlan& p) {
     PlanHost h;
-    plan_host(g, p, h);
+    plan_host(g, p, h, e.host_threads(1 << 20) > 1);
     return plan_upload(e, g, p, h);
 }
 
 // Both plans of one H_eff term group: the host parts on two threads.
 static dmrg_status finish_plans(Engine& e, GB& g1, GemmPlan& p1, GB& g2, GemmPlan& p2) {
     PlanHost h1, h2;
-    std::thread t([&] { plan_host(g1, p1, h1); });
-    plan_host(g2, p2, h2);
+    const bool par = e.host_threads(1 << 20) > 1;
+    std::thread t([&] { plan_host(g1, p1, h1, par); });
+    plan_host(g2, p2, h2, par);
     t.join();
     dmrg_status st = plan_upload(e, g1, p1, h1);
     if (st) return st;
@@ -1239,8 +1249,7 @@ dmrg_status Engine::renormalize(const Enl& en, const OpSet& ops, bool normal_in,
     Buf tbuf;
     TRY(alloc_buf(tbuf, std::max<int64_t>(t_elems, 1) * sizeof(double)));
     GemmPlan p1, p2;
-    TRY(finish_plan(*this, g1, p1));
-    TRY(finish_plan(*this, g2, p2));
+    TRY(finish_plans(*this, g1, p1, g2, p2));
     BufTable bufs{ops.pool.p, out.iso.p, tbuf.p, out.ops.pool.p, tmp.pool.p};
     TRY(run_gemm(dmrgdev::P_F64, bufs, p1));
     TRY(run_gemm(dmrgdev::P_F64, bufs, p2));
@@ -1475,7 +1484,8 @@ dmrg_status Engine::build_heff_plan(Bond& B) {
         int64_t zsize = 0;
         double alg = 0.0;                            // algorithmic flops
     };
-    auto leaves = [&]() { return fail(DMRG_ERR_DEVICE, "internal: H_eff term leaves the target sector"); };
+    // (work runs on several host threads: it reports, the caller fails)
+    auto leaves = [&]() { return DMRG_ERR_DEVICE; };
     auto work = [&](const Term& tm, TermWork& w) -> dmrg_status {
         const Op* A = tm.a >= 0 ? &B.Sops.ops[tm.a] : nullptr;
         const Op* Bo = tm.b >= 0 ? &B.Eops.ops[tm.b] : nullptr;
@@ -1713,9 +1723,27 @@ dmrg_status Engine::build_heff_plan(Bond& B) {
         first = false;
         return DMRG_OK;
     };
-    for (const Term& tm : B.terms) {
-        TermWork w;
-        TRY(work(tm, w));
+    // Every term's blocks and chunks depend only on the bond's structure: they
+    // are formed on up to 16 host threads, then merged in term order (the
+    // plans are those of a serial pass).
+    const size_t nterms = B.terms.size();
+    std::vector<TermWork> works(nterms);
+    {
+        std::vector<dmrg_status> wst(nterms, DMRG_OK);
+        std::atomic<size_t> next(0);
+        auto run = [&] {
+            for (size_t t = next++; t < nterms; t = next++) wst[t] = work(B.terms[t], works[t]);
+        };
+        const int nth = host_threads((int64_t)nterms);
+        std::vector<std::thread> pool;
+        for (int i = 1; i < nth; ++i) pool.emplace_back(run);
+        run();
+        for (auto& th : pool) th.join();
+        for (dmrg_status st : wst)
+            if (st != DMRG_OK) return fail(DMRG_ERR_DEVICE, "internal: H_eff term leaves the target sector");
+    }
+    for (size_t t = 0; t < nterms; ++t) {
+        TermWork w = std::move(works[t]);
         if (z > 0 && z + w.zsize > zbudget) TRY(close_group());
         for (ZOut& zb : w.z) {
             g1.begin();

@@ -2,11 +2,13 @@
 // block-operator catalogue and blocking recipes, work lists for the device
 // kernels, and the sweep / Davidson / truncation control.
 #pragma once
+#include <algorithm>
 #include <array>
 #include <cstdint>
 #include <map>
 #include <memory>
 #include <string>
+#include <thread>
 #include <unordered_map>
 #include <vector>
 
@@ -254,6 +256,13 @@ class Batch;  // products of several contexts launched together (batch.h)
 class Engine {
 public:
     const dmrg_options& options() const { return opt_; }
+    // host threads for a planning loop of n independent items: at most 16 (the
+    // host's share), 1 while dmrg_sweep_many runs contexts side by side
+    int host_threads(int64_t n) const {
+        if (in_many_ || n < 64) return 1;
+        const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+        return (int)std::min<int64_t>(n / 32, std::min(16u, hw));
+    }
     Engine(dmrgdev::Ctx* dev, const dmrg_options& opt) : dev_(dev), opt_(opt) {}
     ~Engine();
 
