@@ -1078,11 +1078,21 @@ bool Engine::enlarge_plan(const Stored& base, char side, const std::vector<QN>& 
     ops = OpSet();
     const int nbase = (int)base.basis.q.size();
     const int64_t nsub = (int64_t)en.sub.size();
-    std::vector<std::pair<int64_t, LcTerm>> contrib;
-    std::vector<LcTerm> terms;
-    for (auto& kf : formulas) {
-        const Formula& f = kf.second;
-        if (f.empty()) continue;
+    // Per formula, its dq, parity and contributions (out sub, in sub, term):
+    // formed on several host threads, each formula on its own, then laid out
+    // in formula order below (block offsets and copies are those of a
+    // serial pass).
+    struct FPlan {
+        QN dq;
+        int par = 0;
+        std::vector<std::pair<int64_t, LcTerm>> contrib;
+    };
+    std::vector<FPlan> fplans(formulas.size());
+    auto plan_formula = [&](size_t fi) {
+        const Formula& f = formulas[fi].second;
+        if (f.empty()) return;
+        FPlan& fp = fplans[fi];
+        std::vector<std::pair<int64_t, LcTerm>>& contrib = fp.contrib;
         // dq and parity from the first term
         QN bdq;
         int bpar = 0;
@@ -1093,13 +1103,12 @@ bool Engine::enlarge_plan(const Stored& base, char side, const std::vector<QN>& 
             bpar = o.par;
         }
         int ds = site_dsig(t0.site);
-        QN dq = ds == 1 ? bdq + delta_[s] : (ds == -1 ? bdq - delta_[s] : bdq);
-        int par = (bpar + site_par(t0.site)) % 2;
+        fp.dq = ds == 1 ? bdq + delta_[s] : (ds == -1 ? bdq - delta_[s] : bdq);
+        fp.par = (bpar + site_par(t0.site)) % 2;
         // contributions (out sub, in sub, term), walking each referenced
         // operator's blocks (a stored operator has at most one block per input
         // sector); grouped by (out, in) with a stable sort, which keeps the
         // term order of the formula inside a group
-        contrib.clear();
         for (const FTerm& t : f) {
             const int tpar = t.ident ? 0 : base.ops.ops[t.refs[0].op].par;
             const auto& els = site_elems(t.site);
@@ -1138,14 +1147,31 @@ bool Engine::enlarge_plan(const Stored& base, char side, const std::vector<QN>& 
                 }
             }
         }
-        if (contrib.empty()) continue;
         std::stable_sort(contrib.begin(), contrib.end(),
                          [](const std::pair<int64_t, LcTerm>& x, const std::pair<int64_t, LcTerm>& y) {
                              return x.first < y.first;
                          });
+    };
+    {
+        std::atomic<size_t> next(0);
+        auto run = [&] {
+            for (size_t fi = next++; fi < formulas.size(); fi = next++) plan_formula(fi);
+        };
+        // the two enlarged blocks are planned side by side: half the threads each
+        const int nth = std::max(1, host_threads((int64_t)formulas.size()) / 2);
+        std::vector<std::thread> pool;
+        for (int t = 1; t < nth; ++t) pool.emplace_back(run);
+        run();
+        for (auto& th : pool) th.join();
+    }
+    std::vector<LcTerm> terms;
+    for (size_t fi = 0; fi < formulas.size(); ++fi) {
+        const FPlan& fp = fplans[fi];
+        const std::vector<std::pair<int64_t, LcTerm>>& contrib = fp.contrib;
+        if (contrib.empty()) continue;
         Op op;
-        op.dq = dq;
-        op.par = par;
+        op.dq = fp.dq;
+        op.par = fp.par;
         for (size_t g0 = 0; g0 < contrib.size();) {
             size_t g1 = g0;
             terms.clear();
@@ -1153,7 +1179,7 @@ bool Engine::enlarge_plan(const Stored& base, char side, const std::vector<QN>& 
             const int i_out = (int)(contrib[g0].first / nsub), i_in = (int)(contrib[g0].first % nsub);
             const Sub& so = en.sub[i_out];
             const Sub& si = en.sub[i_in];
-            if (so.q != si.q + dq) {
+            if (so.q != si.q + fp.dq) {
                 why = "internal: inconsistent blocking formula";
                 return false;
             }
@@ -1163,7 +1189,7 @@ bool Engine::enlarge_plan(const Stored& base, char side, const std::vector<QN>& 
             g0 = g1;
         }
         op.index();
-        ops.add(kf.first, std::move(op));
+        ops.add(formulas[fi].first, std::move(op));
     }
     return true;
 }
@@ -1197,30 +1223,50 @@ dmrg_status Engine::renormalize(const Enl& en, const OpSet& ops, bool normal_in,
         Op op;
     };
     std::vector<Pending> pend;
+    // per operator, its blocks grouped by (m_out, m_in) and within a group by
+    // output sub-sector: formed on several host threads, then planned in
+    // operator order below (pool offsets and plans are those of a serial pass)
+    typedef std::vector<std::pair<int, std::vector<const Blk*>>> ByOut;
+    struct OpGroups {
+        std::vector<std::pair<std::pair<int, int>, ByOut>> groups;
+    };
+    std::vector<OpGroups> og(ops.ops.size());
+    auto group_op = [&](size_t o) {
+        std::map<std::pair<int, int>, std::map<int, std::vector<const Blk*>>> groups;
+        for (const Blk& b : ops.ops[o].blk) {
+            int mo = en.sub[b.out].m, mi = en.sub[b.in].m;
+            if (newidx[mo] < 0 || newidx[mi] < 0) continue;
+            groups[{mo, mi}][b.out].push_back(&b);
+        }
+        for (auto& gkv : groups) og[o].groups.push_back({gkv.first, ByOut(gkv.second.begin(), gkv.second.end())});
+    };
+    {
+        std::atomic<size_t> next(0);
+        auto run = [&] {
+            for (size_t o = next++; o < ops.ops.size(); o = next++) group_op(o);
+        };
+        const int nth = host_threads((int64_t)ops.ops.size());
+        std::vector<std::thread> pool;
+        for (int t = 1; t < nth; ++t) pool.emplace_back(run);
+        run();
+        for (auto& th : pool) th.join();
+    }
     for (size_t o = 0; o < ops.ops.size(); ++o) {
         const Key& key = ops.keys[o];
         const Op& op = ops.ops[o];
         bool to_tmp = transition && (key.k == 'A' || key.k == 'B');
         OpSet& dst = to_tmp ? tmp : out.ops;
-        // group blocks by (m_out, m_in)
-        std::map<std::pair<int, int>, std::vector<const Blk*>> groups;
-        for (const Blk& b : op.blk) {
-            int mo = en.sub[b.out].m, mi = en.sub[b.in].m;
-            if (newidx[mo] < 0 || newidx[mi] < 0) continue;
-            groups[{mo, mi}].push_back(&b);
-        }
-        if (groups.empty()) continue;
+        if (og[o].groups.empty()) continue;
         Op nop;
         nop.dq = op.dq;
         nop.par = op.par;
-        for (auto& gkv : groups) {
+        for (auto& gkv : og[o].groups) {
             int mo = gkv.first.first, mi = gkv.first.second;
             int xo = newidx[mo], xi = newidx[mi];
             int ko = kdim[xo], ki = kdim[xi];
             Blk nb{xo, xi, dst.alloc_block(ko, ki), ko, ki};
             // phase 1: T[(i_out)] = sum_{i_in} O[i_out, i_in] U_mi[rows i_in]  (d(i_out) x ki)
-            std::map<int, std::vector<const Blk*>> by_out;
-            for (const Blk* b : gkv.second) by_out[b->out].push_back(b);
+            const ByOut& by_out = gkv.second;
             g2.begin();
             for (auto& bo : by_out) {
                 const Sub& so = en.sub[bo.first];
