@@ -238,14 +238,14 @@ dmrg_status Engine::run_gemm(int prec, BufTable bufs, const GemmPlan& p, int cpr
         }
     }
     dmrgdev::Sched sc;
-    sc.wg_off = p.wg_off.as<int32_t>();
+    sc.wg_off = p.wg_off;
     sc.nwg = p.nwg;
     sc.nfull = p.nfull;
     sc.ntasks = p.ntasks;
-    DEV(dmrgdev::gemm(dev_, prec, cprec, bufs.data(), p.tasks.as<GemmTask>(), sc, p.chunks.as<GemmChunk>(), kind,
+    DEV(dmrgdev::gemm(dev_, prec, cprec, bufs.data(), p.tasks, sc, p.chunks, kind,
                       ev_start, ev_stop));
     if (p.nreds)
-        DEV(dmrgdev::gemm_reduce(dev_, cprec, bufs.data(), p.reds.as<dmrgdev::RedTask>(), p.nreds));
+        DEV(dmrgdev::gemm_reduce(dev_, cprec, bufs.data(), p.reds, p.nreds));
     return DMRG_OK;
 }
 
@@ -502,14 +502,26 @@ static void plan_host(const GB& g, GemmPlan& p, PlanHost& h, bool parallel = tru
     p.elems = g.elems;
 }
 
+// The four lists of a plan go up in one copy, laid out at 256-byte offsets
+// in one device block.
 static dmrg_status plan_upload(Engine& e, const GB& g, GemmPlan& p, const PlanHost& h) {
-    dmrg_status st = e.upload(p.tasks, h.tasks);
+    auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    const size_t bt = h.tasks.size() * sizeof(GemmTask), bw = h.wg_off.size() * sizeof(int32_t),
+                 br = h.reds.size() * sizeof(dmrgdev::RedTask), bc = g.chunks.size() * sizeof(GemmChunk);
+    const size_t ot = 0, ow = al(bt), orr = ow + al(bw), oc = orr + al(br);
+    std::vector<char> img(std::max<size_t>(oc + al(bc), 8));
+    if (bt) std::memcpy(img.data() + ot, h.tasks.data(), bt);
+    if (bw) std::memcpy(img.data() + ow, h.wg_off.data(), bw);
+    if (br) std::memcpy(img.data() + orr, h.reds.data(), br);
+    if (bc) std::memcpy(img.data() + oc, g.chunks.data(), bc);
+    dmrg_status st = e.upload(p.dev, img);
     if (st) return st;
-    st = e.upload(p.wg_off, h.wg_off);
-    if (st) return st;
-    st = e.upload(p.reds, h.reds);
-    if (st) return st;
-    return e.upload(p.chunks, g.chunks);
+    char* base = p.dev.as<char>();
+    p.tasks = bt ? reinterpret_cast<GemmTask*>(base + ot) : nullptr;
+    p.wg_off = bw ? reinterpret_cast<int32_t*>(base + ow) : nullptr;
+    p.reds = br ? reinterpret_cast<dmrgdev::RedTask*>(base + orr) : nullptr;
+    p.chunks = bc ? reinterpret_cast<GemmChunk*>(base + oc) : nullptr;
+    return DMRG_OK;
 }
 
 static dmrg_status finish_plan(Engine& e, GB& g, GemmPlan& p) {
@@ -2022,11 +2034,11 @@ dmrg_status Engine::heff_batched(Bond& B, const double* x, double* y, int prec) 
     for (int ph = 0; ph < 3; ++ph) {
         const GemmPlan& p = *ps[ph];
         for (int i = 0; i < dmrgdev::kMaxBufs; ++i) r.plan[ph].bufs[i] = r.red[ph].bufs[i] = bufs[i];
-        r.plan[ph].tasks = p.tasks.as<GemmTask>();
-        r.plan[ph].chunks = p.chunks.as<GemmChunk>();
-        r.plan[ph].sc = dmrgdev::Sched{p.wg_off.as<int32_t>(), std::max(1, p.nwg), p.nfull, p.ntasks};
+        r.plan[ph].tasks = p.tasks;
+        r.plan[ph].chunks = p.chunks;
+        r.plan[ph].sc = dmrgdev::Sched{p.wg_off, std::max(1, p.nwg), p.nfull, p.ntasks};
         r.nwg[ph] = p.ntasks ? std::max(1, p.nwg) : 0;
-        r.red[ph].reds = p.reds.as<dmrgdev::RedTask>();
+        r.red[ph].reds = p.reds;
         r.nreds[ph] = p.nreds;
     }
     r.ready = ev_ready_;

@@ -216,7 +216,12 @@ struct Term {
 using BufTable = std::array<void*, dmrgdev::kMaxBufs>;
 
 struct GemmPlan {
-    Buf tasks, chunks, reds, wg_off;
+    // task, chunk, reduction and schedule lists: one device allocation, one upload
+    Buf dev;
+    dmrgdev::GemmTask* tasks = nullptr;
+    dmrgdev::GemmChunk* chunks = nullptr;
+    dmrgdev::RedTask* reds = nullptr;
+    int32_t* wg_off = nullptr;
     int ntasks = 0, nreds = 0;
     int nwg = 0, nfull = 0;   // persistent work-groups; tasks with chunks
     int64_t nslots = 0;     // split-K partial tiles
