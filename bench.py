@@ -30,6 +30,7 @@ sys.path.insert(0, ROOT)
 
 PEAK = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}   # dense MFMA TFLOP/s, MI355X
 PREC = {"fp64": 0, "fp32": 1, "bf16": 2}
+SWEEP_CRIT_MEV = 1e-4   # the paper sweeps until the energy changes by less than this between sweeps
 HBM_PEAK = 8000.0   # GB/s
 
 
@@ -61,6 +62,7 @@ def run_schedule(workload, prec: str, warmup: int, steps: int, D_main: int, seed
     torch.cuda.synchronize()
     tot = {}
     walls = []
+    deltas = []        # energy change against the previous sweep, per timed sweep (MeV)
     energy = None
     # host clock readings around the timed sweeps, so that a profiler's trace
     # (whose timestamps come from one of these clocks) can pick out their launches
@@ -73,10 +75,12 @@ def run_schedule(workload, prec: str, warmup: int, steps: int, D_main: int, seed
         walls.append(time.perf_counter() - t)
         energy = r["energy"]
         energies.append(energy)
+        deltas.append(r["delta_energy"])
         for key, v in r.items():
-            if isinstance(v, (int, float)) and key not in ("energy", "last_theta", "code", "status"):
+            if isinstance(v, (int, float)) and key not in ("energy", "last_theta", "code", "status",
+                                                           "delta_energy"):
                 tot[key] = tot.get(key, 0) + v
-        log(f"[{prec}] timed sweep {k} D={D_main}: E={r['energy']:.9f} {walls[-1]:.2f}s "
+        log(f"[{prec}] timed sweep {k} D={D_main}: E={r['energy']:.9f} dE={r['delta_energy']:.2e} {walls[-1]:.2f}s "
             f"products lo/64={r['products_low']}/{r['products_fp64']} not converged {r['not_converged']} "
             f"heff {r['heff_flops'] / max(r['heff_seconds'], 1e-12) / 1e12:.2f} TF/s; "
             f"time in products {r['heff_seconds']:.2f}s, truncation+renorm+prediction "
@@ -96,7 +100,7 @@ def run_schedule(workload, prec: str, warmup: int, steps: int, D_main: int, seed
             f"{chk['solves']} pairs, max |theta - theta_fp64| / |theta_fp64| = {chk['max_rel']:.3e} "
             f"({time.perf_counter() - t:.1f}s)")
     ctx.close()
-    return dict(energy=energy, walls=walls, tot=tot, energies=energies, check=chk, window=win)
+    return dict(energy=energy, walls=walls, tot=tot, energies=energies, deltas=deltas, check=chk, window=win)
 
 
 def plateaus(name: str, prec: str, Ds, per: int, tol: float, trunc_eps: float = 0.0, d_min: int = 0,
@@ -139,6 +143,80 @@ def plateaus(name: str, prec: str, Ds, per: int, tol: float, trunc_eps: float = 
                           "not_converged": r["not_converged"], "gemm_phases": g,
                           "device_mem_used_gb": (total - free) / 1e9}), flush=True)
     ctx.close()
+
+
+def converge(name: str, prec: str, Ds, max_sweeps: int, budget_s: float, tol: float):
+    """The paper's stopping rule along a D schedule: at each D, sweep until the
+    energy changes by less than 1e-4 MeV between two sweeps (at most
+    `max_sweeps` sweeps or `budget_s` seconds per D).  One JSON line per D,
+    then the paper's extrapolation E(M) = E_inf + X1 M^X2 over the D values
+    whose sweeps met the rule.  Returns {D: energy}."""
+    import torch
+    import paper_1507_00161_amd as pk
+    from workloads import WORKLOADS
+    h = WORKLOADS[name].hamiltonian()
+    sp = h.space
+    ctx = pk.Context(precision=PREC[prec], davidson_tol=tol, noise=1e-4, noise_sweeps=2, seed=1507)
+    ctx.load_hamiltonian(sp.species, sp.two_m, h.eps, h.V.ravel(), h.n_p, h.n_n, h.two_M)
+    out = {}
+    for D in Ds:
+        t_plateau = time.perf_counter()
+        energies, deltas, walls = [], [], []
+        met = False
+        for k in range(max_sweeps):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            r = ctx.sweep(D)
+            torch.cuda.synchronize()
+            walls.append(time.perf_counter() - t)
+            energies.append(r["energy"])
+            # the first sweep at a new D is compared with the last one at the previous D;
+            # the rule is applied from the second sweep of the plateau on
+            d = r["delta_energy"]
+            deltas.append(d)
+            log(f"[{name} {prec}] D={D} sweep {k}: E={r['energy']:.9f} dE={d:.3e} {walls[-1]:.2f}s "
+                f"not converged {r['not_converged']}")
+            if k >= 1 and abs(d) < SWEEP_CRIT_MEV:
+                met = True
+                break
+            if time.perf_counter() - t_plateau > budget_s:
+                break
+        out[D] = {"energy": energies[-1], "met": met}
+        print(json.dumps({"mode": "converge", "workload": name, "precision": prec, "D": D,
+                          "criterion_MeV": SWEEP_CRIT_MEV, "met": met, "sweeps": len(energies),
+                          "energy": energies[-1], "delta_E_MeV_last": deltas[-1],
+                          "delta_E_MeV": deltas, "s_per_sweep_mean": sum(walls) / len(walls),
+                          "plateau_s": time.perf_counter() - t_plateau}), flush=True)
+    ctx.close()
+    pts = sorted((D, v["energy"]) for D, v in out.items() if v["met"])
+    fit = extrapolate(pts)
+    print(json.dumps({"mode": "extrapolation", "workload": name, "precision": prec,
+                      "points": pts, "fit": fit}), flush=True)
+    return out
+
+
+def extrapolate(pts):
+    """E(M) = E_inf + X1 M^X2 through (M, E) points (least squares; exact
+    through three points).  None when fewer than three points or no fit."""
+    if len(pts) < 3:
+        return None
+    import numpy as np
+    from scipy.optimize import least_squares
+    M = np.array([p[0] for p in pts], float)
+    E = np.array([p[1] for p in pts], float)
+
+    def lin(x2):   # for fixed X2 the model is linear in (E_inf, X1)
+        A = np.stack([np.ones_like(M), M ** x2], 1)
+        c, *_ = np.linalg.lstsq(A, E, rcond=None)
+        return c, A @ c - E
+    try:
+        r = least_squares(lambda x: lin(x[0])[1], x0=[-0.5], bounds=([-6.0], [-1e-3]), jac="3-point",
+                          xtol=1e-15, ftol=1e-15, gtol=1e-15)
+        x2 = float(r.x[0])
+        c, res = lin(x2)
+    except Exception:
+        return None
+    return {"E_inf": float(c[0]), "X1": float(c[1]), "X2": x2, "max_residual_MeV": float(np.abs(res).max())}
 
 
 def preprocess(name: str, prec: str, D_pre: int, sweeps_pre: int, Ds, per: int, tol: float):
@@ -560,6 +638,10 @@ def main():
                     help="measuring sweeps at --D-pre, Fiedler ordering, then --D-list plateaus in both orders")
     ap.add_argument("--D-pre", type=int, default=256)
     ap.add_argument("--sweeps-pre", type=int, default=2)
+    ap.add_argument("--converge", metavar="WORKLOAD",
+                    help="at each --D-list value, sweep until |dE| < 1e-4 MeV between sweeps; then E(M) fit")
+    ap.add_argument("--max-sweeps", type=int, default=60, help="converge: most sweeps per D")
+    ap.add_argument("--budget-s", type=float, default=300.0, help="converge: most seconds per D")
     ap.add_argument("--batched", type=int, metavar="K",
                     help="independent small solves: K instances one at a time vs dmrg_sweep_many")
     args = ap.parse_args()
@@ -579,6 +661,19 @@ def main():
         for p in args.precisions.split(","):
             preprocess(args.preprocess, p, args.D_pre, args.sweeps_pre, [int(x) for x in args.D_list.split(",")],
                        args.per, args.tol)
+        return
+    if args.converge:
+        got = {}
+        for p in [x.strip() for x in args.precisions.split(",") if x.strip()]:
+            got[p] = converge(args.converge, p, [int(x) for x in args.D_list.split(",")], args.max_sweeps,
+                              args.budget_s, args.tol)
+        if "fp64" in got:
+            for p, g in got.items():
+                if p == "fp64":
+                    continue
+                cmp = {D: abs(v["energy"] - got["fp64"][D]["energy"]) / abs(got["fp64"][D]["energy"])
+                       for D, v in g.items() if v["met"] and got["fp64"][D]["met"]}
+                print(json.dumps({"mode": "converged_vs_fp64", "precision": p, "rel": cmp}), flush=True)
         return
     if args.plateaus:
         for p in [x.strip() for x in args.precisions.split(",") if x.strip()]:
@@ -657,7 +752,9 @@ def main():
         out[f"{p}_run"] = {"energy": r["energy"], "ms_per_sweep": 1e3 * sum(r["walls"]) / len(r["walls"]),
                            "heff_tflops": tt["heff_flops"] / max(tt["heff_seconds"], 1e-12) / 1e12,
                            "products_low": int(tt["products_low"]), "products_fp64": int(tt["products_fp64"]),
-                           "heff_seconds": tt["heff_seconds"]}
+                           "heff_seconds": tt["heff_seconds"],
+                           "delta_E_MeV_timed": r["deltas"],
+                           "paper_sweep_criterion_met": bool(r["deltas"]) and abs(r["deltas"][-1]) < SWEEP_CRIT_MEV}
     if "fp64" in res and main_p != "fp64":
         e64, em = res["fp64"]["energy"], R["energy"]
         # sweep by sweep along the two trajectories (same schedule, same start)

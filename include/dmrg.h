@@ -149,6 +149,11 @@ typedef struct dmrg_sweep_stats {
      * largest |theta - theta_fp64| / |theta_fp64| over them */
     int64_t check_solves;
     double check_max_rel;
+    /* energy minus that of the previous full sweep of this context (MeV);
+     * NaN for the first sweep after the blocks were set up (first call, new
+     * ordering, reloaded Hamiltonian) and for statistics of an unfinished
+     * sweep.  The paper stops sweeping once |delta_energy| < 1e-4 MeV. */
+    double delta_energy;
 } dmrg_sweep_stats;
 
 typedef struct dmrg_ctx dmrg_ctx;

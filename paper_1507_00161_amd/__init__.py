@@ -55,7 +55,8 @@ class SweepStats(ctypes.Structure):
                 ("energy_excited", ctypes.c_double), ("measure_seconds", ctypes.c_double),
                 ("heff_flops_executed", ctypes.c_double),
                 ("gemm1_issued_flops", ctypes.c_double), ("gemm2_issued_flops", ctypes.c_double),
-                ("check_solves", ctypes.c_int64), ("check_max_rel", ctypes.c_double)]
+                ("check_solves", ctypes.c_int64), ("check_max_rel", ctypes.c_double),
+                ("delta_energy", ctypes.c_double)]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}

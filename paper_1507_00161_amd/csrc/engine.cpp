@@ -21,6 +21,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <limits>
 #include <map>
 #include <numeric>
 #include <queue>
@@ -634,6 +635,7 @@ dmrg_status Engine::load(int n, const int32_t* species, const int32_t* two_m, co
     cideas_ = false;
     meas_valid_ = false;
     have_energy_ = false;
+    have_prev_sweep_ = false;
     sweeps_done_ = 0;
     for (int i = 0; i < n; ++i) {
         if (species[i] != 0 && species[i] != 1) return fail(DMRG_ERR_ARG, "species must be 0 or 1");
@@ -2541,6 +2543,7 @@ dmrg_status Engine::initialize(int D) {
     bond_ = 0;
     fresh_ = false;
     sweeps_done_ = 0;
+    have_prev_sweep_ = false;
     TRY(setup_bond(0, cur_));
     TRY(random_psi(*cur_, psi_));
     if (opt_.n_states == 2) TRY(random_psi(*cur_, psi1_));
@@ -3077,6 +3080,10 @@ dmrg_status Engine::steps(const int32_t* ordering, int D, int64_t max_steps, boo
                 acc_.energy = sweep_min_;
                 acc_.energy_excited = opt_.n_states == 2 ? sweep_min1_ : 0.0;
                 acc_.last_theta = theta_;
+                acc_.delta_energy = have_prev_sweep_ ? sweep_min_ - prev_sweep_energy_
+                                                     : std::numeric_limits<double>::quiet_NaN();
+                prev_sweep_energy_ = sweep_min_;
+                have_prev_sweep_ = true;
                 acc_.sweep_seconds = now() - t0;
                 if (st) *st = acc_;
                 sweep_steps_ = 0;
@@ -3103,6 +3110,7 @@ dmrg_status Engine::steps(const int32_t* ordering, int D, int64_t max_steps, boo
     acc_.energy = sweep_min_;
     acc_.energy_excited = opt_.n_states == 2 ? sweep_min1_ : 0.0;
     acc_.last_theta = theta_;
+    acc_.delta_energy = std::numeric_limits<double>::quiet_NaN();   // the sweep is not finished
     acc_.sweep_seconds += now() - t0;
     if (st) *st = acc_;
     return ret;

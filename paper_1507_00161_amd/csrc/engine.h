@@ -359,6 +359,8 @@ private:
     double theta_ = 0.0;
     bool have_energy_ = false;
     double energy_ = 0.0;
+    double prev_sweep_energy_ = 0.0;   // energy of the last full sweep since the blocks were set up
+    bool have_prev_sweep_ = false;
     double sweep_min_ = 0.0;
     double sweep_min1_ = 0.0;   // second state
     double theta1_ = 0.0;

@@ -14,6 +14,7 @@
   pairing closed form at the pf 8p+8n size.
 """
 import json
+import math
 import os
 
 import numpy as np
@@ -231,12 +232,19 @@ def test_sweep_energies_match_oracle(pk, name, precision, rtol):
     sp = h.space
     order = None if case["ordering_seed"] is None else random_ordering(sp.n_sites, case["ordering_seed"])
     c = _ctx(pk, h, precision=precision, **g["options"])
+    prev = None
     for D, e_ref in zip(case["D"], case["energies"]):
         r = c.sweep(D, order)
         assert r["code"] == 0
         assert abs(r["energy"] - e_ref) <= rtol * abs(e_ref), (D, r["energy"], e_ref)
         if "exact" in case:
             assert r["energy"] >= case["exact"] - 1e-9        # variational bound
+        # the energy change between sweeps that the paper's stopping rule reads
+        if prev is None:
+            assert math.isnan(r["delta_energy"])
+        else:
+            assert r["delta_energy"] == r["energy"] - prev
+        prev = r["energy"]
     assert c.energy() == r["energy"]
 
 
