@@ -3,11 +3,14 @@
 // Hot path: `gemm` is a grouped, multi-chunk GEMM.  One work-group (4 waves)
 // owns one 64x64 output tile of one sector block and accumulates every chunk
 // (term x input sub-block) that lands on it, so an output is written once,
-// without atomics.  Operands are staged through LDS in 16-deep K slices
-// (transposes are resolved while staging) and multiplied on the matrix cores:
-// v_mfma_f64_16x16x4f64 (FP64), v_mfma_f32_16x16x4f32 (FP32) and
-// v_mfma_f32_16x16x32_bf16 (BF16 operands, FP32 accumulation).  Each wave
-// holds a 32x32 quarter of the tile as 2x2 MFMA blocks.
+// without atomics.  Operands are staged through LDS in K slices and
+// multiplied on the matrix cores: v_mfma_f64_16x16x4f64 (FP64),
+// v_mfma_f32_16x16x4f32 (FP32) and v_mfma_f32_16x16x32_bf16 (BF16 operands,
+// FP32 accumulation).  FP64 and BF16 slices go through registers into LDS
+// (transposes resolved while staging, gemm_body); FP32 slices are loaded
+// straight into LDS and transposed operands are read down their columns
+// (gemm_body_f32dma).  Each wave holds a 32x32 quarter of the tile as 2x2
+// MFMA blocks.
 #include <hip/hip_runtime.h>
 #include <hip/hip_ext.h>
 #include <rocblas/rocblas.h>
@@ -492,7 +495,8 @@ struct LdsBufs {
     }
 };
 
-// Persistent grouped GEMM.  Work-group w runs its task list
+// Persistent grouped GEMM (the FP64 and BF16 instantiations; FP32 runs
+// gemm_body_f32dma below).  Work-group w runs its task list
 // [wg_off[w], wg_off[w+1]) (balanced on the host).  One software pipeline runs
 // over the K slices of all its chunks and tasks: the next slice's global loads
 // (possibly of the next task) are in flight while the MFMAs consume the current
@@ -744,19 +748,292 @@ __device__ __forceinline__ void gemm_body(const BS bufs, const GemmTask* __restr
     }
 }
 
+// FP32 grouped GEMM with direct-to-LDS loads.  Each K slice (32 deep) of a
+// 64-row operand tile is 8 KB, written into LDS by 16-byte buffer loads that
+// bypass the registers (two per wave and operand); each load of a wave fills
+// 1 KB of LDS in lane order, so the layout is chosen through which global
+// chunk each lane fetches:
+//  - K contiguous: rows of 32 k (128 B); 16-byte chunk c of row r sits at
+//    position c ^ swz_k(r) of its row;
+//  - M (or N) contiguous: k-rows of 64 m (256 B); chunk g (4 rows) of k-row kr
+//    sits at position g ^ swz_m(kr).
+// The swizzles keep the fragment reads (16-byte reads of one row's chunk, or
+// 4-byte reads down a k-column) on distinct banks.  MFMA step q of lane group
+// fk takes k = 16 (q / 4) + 4 fk + q % 4 (any one-to-one map works when both
+// operands use it): a K-contiguous fragment is one chunk per half slice, and
+// a slice whose chunk ends in its first half skips the second half's steps.
+// One barrier per slice: after it, the next slice's loads go into the other
+// buffer, which every wave has finished reading.
+// Bounds: chunks past the operand's K or rows are fetched with an offset past
+// the resource range and land as zeros; the range is the tile's extent, so a
+// chunk that crosses it gets zeros beyond it without a memory access.  Values
+// past K that a K-contiguous chunk carries from inside the block are replaced
+// by zero after the fragment read; values of rows past the tile's edge only
+// reach output rows that are not written.
+__device__ __forceinline__ int swz_k(int r) { return (r ^ (r >> 3)) & 7; }
+__device__ __forceinline__ int swz_m(int kr) { return 4 * ((kr >> 2) & 3); }
+typedef __attribute__((address_space(3))) void* lds_ptr_t;
+// this wave's two 1 KB pieces of one operand's slice into the LDS tile `dst`
+// (2048 floats); `P` is the operand block, rows r0 .. r0 + rmax - 1 of it
+__device__ __forceinline__ void dma_slice(float* dst, const float* P, bool along_k, int ld, int r0, int rmax,
+                                          int k0, int K, int wave, int lane) {
+    const int ext = along_k ? ((r0 + rmax - 1) * ld + K) * 4 : ((K - 1) * ld + r0 + rmax) * 4;
+    // uniform over the wave: kept in a scalar register, as the resource must be
+    const int range = __builtin_amdgcn_readfirstlane(ext < 0 ? 0 : (ext > kRecords ? kRecords : ext));
+    const __amdgpu_buffer_rsrc_t rs =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(P), (short)0, range, 0x00020000);
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        int off, lds;
+        if (along_k) {
+            const int R0 = 16 * wave + 8 * i, r = R0 + (lane >> 3);
+            const int c = (lane & 7) ^ swz_k(r);
+            const int o = ((r0 + r) * ld + k0 + 4 * c) * 4;
+            off = (r < rmax) & (k0 + 4 * c < K) ? o : kOutside;
+            lds = R0 * 32;
+        } else {
+            const int K0 = 8 * wave + 4 * i, kr = K0 + (lane >> 4);
+            const int g = (lane & 15) ^ swz_m(kr);
+            const int o = ((k0 + kr) * ld + r0 + 4 * g) * 4;
+            off = (k0 + kr < K) & (4 * g < rmax) ? o : kOutside;
+            lds = K0 * 64;
+        }
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (lds_ptr_t)(dst + lds), 16, off, 0, 0, 0);
+    }
+}
+// one operand's fragments (two 16-row blocks, 8 k each) of the slice in `src`
+__device__ __forceinline__ void frag_read(float (&f)[2][8], const float* src, bool along_k, int w0, int fr, int fk) {
+    if (along_k) {
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+            const int r = w0 + 16 * a + fr;
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int slot = (4 * h + fk) ^ swz_k(r);
+                const f4_t v = *(const f4_t*)&src[r * 32 + slot * 4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) f[a][4 * h + j] = v[j];
+            }
+        }
+    } else {
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+            const int r = w0 + 16 * a + fr;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int kr = 16 * (q >> 2) + 4 * fk + (q & 3);
+                const int slot = (r >> 2) ^ swz_m(kr);
+                f[a][q] = src[kr * 64 + slot * 4 + (r & 3)];
+            }
+        }
+    }
+}
+
+template <class TC, class BS>
+__device__ __forceinline__ void gemm_body_f32dma(const BS bufs, const GemmTask* __restrict__ tasks_g,
+                                                 const GemmChunk* __restrict__ chunks_g, const Sched& sc, int wg,
+                                                 int nwg) {
+    const cptr<GemmTask> tasks = as_const(tasks_g);
+    const cptr<GemmChunk> chunks = as_const(chunks_g);
+    const cptr<int32_t> wg_off = as_const(sc.wg_off);
+    typedef MmaTraits<float> MT;
+    // two buffers per operand, as separate objects so that the compiler can tell
+    // the loads into one from the reads of the other
+    __shared__ __attribute__((aligned(16))) float A0[2048], A1[2048], B0[2048], B1[2048];
+    const int tid = threadIdx.x;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int lane = tid & 63;
+    const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;   // wave quadrant
+    const int fr = lane & 15, fk = lane >> 4;
+    int ti = wg_off[wg];
+    const int hi = wg_off[wg + 1];
+    f4_t acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = f4_t{0, 0, 0, 0};
+    auto ptr_a = [&](const GemmChunk& ch) { return (const float*)bufs.get(ch.a_buf) + ch.a_off; };
+    auto ptr_b = [&](const GemmChunk& ch) { return (const float*)bufs.get(ch.b_buf) + ch.b_off; };
+    auto dma = [&](float* da, float* db, const GemmTask& t, const GemmChunk& ch, const float* pa, const float* pb,
+                   int k0) {
+        dma_slice(da, pa, !ch.a_trans, ch.lda, t.m0, t.mt, k0, ch.K, wave, lane);
+        dma_slice(db, pb, ch.b_trans, ch.ldb, t.n0, t.nt, k0, ch.K, wave, lane);
+    };
+    auto compute = [&](const float* sa, const float* sb, const GemmTask& t, const GemmChunk& ch, int k0) {
+        if (!(wm < t.mt && wn < t.nt)) return;
+        const int kv = ch.K - k0;
+        const bool am1 = wm + 16 < t.mt, bm1 = wn + 16 < t.nt;
+        const bool ak = !ch.a_trans, bk = ch.b_trans;
+        float fa[2][8], fb[2][8];
+        frag_read(fa, sa, ak, wm, fr, fk);
+        frag_read(fb, sb, bk, wn, fr, fk);
+        if (kv < 32 && (ak || bk)) {
+            const int lim = kv - 4 * fk;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const bool ok = 16 * (q >> 2) + (q & 3) < lim;
+#pragma unroll
+                for (int i = 0; i < 2; ++i) {
+                    if (ak) fa[i][q] = ok ? fa[i][q] : 0.0f;
+                    if (bk) fb[i][q] = ok ? fb[i][q] : 0.0f;
+                }
+            }
+        }
+        const float alpha = (float)ch.alpha;
+        if (alpha != 1.0f) {
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+#pragma unroll
+                for (int i = 0; i < 2; ++i) fa[i][q] *= alpha;
+        }
+        const int nq = kv > 16 ? 8 : 4;
+        if (am1 && bm1) {
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+                if (q < nq) {
+#pragma unroll
+                    for (int a = 0; a < 2; ++a)
+#pragma unroll
+                        for (int b = 0; b < 2; ++b) acc[a][b] = MT::mma(fa[a][q], fb[b][q], acc[a][b]);
+                }
+        } else {
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+                if (q < nq) {
+                    acc[0][0] = MT::mma(fa[0][q], fb[0][q], acc[0][0]);
+                    if (bm1) acc[0][1] = MT::mma(fa[0][q], fb[1][q], acc[0][1]);
+                    if (am1) acc[1][0] = MT::mma(fa[1][q], fb[0][q], acc[1][0]);
+                }
+        }
+    };
+    auto epilogue = [&](const GemmTask& t) {
+        TC* C = (TC*)bufs.get(t.c_buf) + t.c_off;
+        const int64_t ldc = t.c_local ? TN : t.ldc;
+        const int64_t base = t.c_local ? 0 : (int64_t)t.m0 * t.ldc + t.n0;
+        TC old[2][2][4];
+        if (t.beta) {
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < 2; ++b)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int row = wm + a * 16 + MT::row(lane, r);
+                        const int col = wn + b * 16 + (lane & 15);
+                        const bool in = row < t.mt && col < t.nt;
+                        old[a][b][r] = C[in ? base + (int64_t)row * ldc + col : base];
+                    }
+        }
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int row = wm + a * 16 + MT::row(lane, r);
+                    const int col = wn + b * 16 + (lane & 15);
+                    if (row < t.mt && col < t.nt) {
+                        double v = (double)acc[a][b][r];
+                        if (t.beta) v += from_out<TC>(old[a][b][r]);
+                        C[base + (int64_t)row * ldc + col] = to_out<TC>(v);
+                    }
+                    acc[a][b][r] = 0;
+                }
+    };
+    if (ti < hi) {
+        GemmTask tk = ldc(tasks, ti);
+        int c = tk.chunk_begin;
+        GemmChunk ch = ldc(chunks, c);
+        const float* pa = ptr_a(ch);
+        const float* pb = ptr_b(ch);
+        int k0 = 0;
+        int pti = ti + 1;
+        GemmTask ptk = tk;
+        if (pti < hi) ptk = ldc(tasks, pti);
+        dma(A0, B0, tk, ch, pa, pb, 0);
+        // one slice: wait for its loads, start the successor's loads into the
+        // other buffers, then the MFMAs on this one
+        auto step = [&](const float* sa, const float* sb, float* na, float* nb) -> bool {
+            GemmTask ntk = tk;
+            int nc = c, nk0 = k0 + 32;
+            GemmChunk nch = ch;
+            const float* npa = pa;
+            const float* npb = pb;
+            bool newtask = false, more = true;
+            if (nk0 >= ch.K) {
+                nk0 = 0;
+                nc = c + 1;
+                if (nc < tk.chunk_end) {
+                    nch = ldc(chunks, nc);
+                } else {
+                    newtask = true;
+                    more = pti < hi;
+                    if (more) {
+                        ntk = ptk;
+                        nc = ntk.chunk_begin;
+                        nch = ldc(chunks, nc);
+                    }
+                }
+                npa = ptr_a(nch);
+                npb = ptr_b(nch);
+            }
+            __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0): this wave's loads of the slice are in LDS
+            __syncthreads();                       // everyone's are; the other buffers are free
+            if (more) dma(na, nb, ntk, nch, npa, npb, nk0);
+            compute(sa, sb, tk, ch, k0);
+            if (newtask) {
+                epilogue(tk);
+                if (more) {
+                    ti = pti;
+                    pti = ti + 1;
+                    if (pti < hi) ptk = ldc(tasks, pti);
+                }
+            }
+            tk = ntk;
+            c = nc;
+            ch = nch;
+            pa = npa;
+            pb = npb;
+            k0 = nk0;
+            return more;
+        };
+        while (step(A0, B0, A1, B1) && step(A1, B1, A0, B0)) {
+        }
+    }
+    // tasks without chunks: clear their tile (beta = 0) or leave it (beta = 1)
+    for (int t = sc.nfull + wg; t < sc.ntasks; t += nwg) {
+        const GemmTask z = ldc(tasks, t);
+        if (z.beta) continue;
+        TC* C = (TC*)bufs.get(z.c_buf) + z.c_off;
+        const int64_t ldc = z.c_local ? TN : z.ldc;
+        const int64_t base = z.c_local ? 0 : (int64_t)z.m0 * z.ldc + z.n0;
+        for (int e = tid; e < TM * TN; e += NTH) {
+            const int r = e / TN, q = e % TN;
+            if (r < z.mt && q < z.nt) C[base + (int64_t)r * ldc + q] = (TC)0;
+        }
+    }
+}
+
 // The same body under three names, so that profiles separate the two
 // H_eff phases from the renormalisation and prediction GEMMs.
+// FP32 products use the direct-to-LDS body, the other precisions the staged one
+template <class T, class TC, int BK, class BS>
+__device__ __forceinline__ void any_body(const BS bufs, const GemmTask* t, const GemmChunk* c, const Sched& s, int wg,
+                                         int nwg) {
+    if constexpr (sizeof(T) == 4) gemm_body_f32dma<TC>(bufs, t, c, s, wg, nwg);
+    else gemm_body<T, TC, BK>(bufs, t, c, s, wg, nwg);
+}
 template <class T, class TC, int BK>
 __global__ void __launch_bounds__(NTH, 4) k_gemm(Bufs b, const GemmTask* t, const GemmChunk* c, Sched s) {
-    gemm_body<T, TC, BK>(ArgBufs{b}, t, c, s, blockIdx.x, gridDim.x);
+    any_body<T, TC, BK>(ArgBufs{b}, t, c, s, blockIdx.x, gridDim.x);
 }
 template <class T, class TC, int BK>
 __global__ void __launch_bounds__(NTH, 4) k_heff_z(Bufs b, const GemmTask* t, const GemmChunk* c, Sched s) {
-    gemm_body<T, TC, BK>(ArgBufs{b}, t, c, s, blockIdx.x, gridDim.x);
+    any_body<T, TC, BK>(ArgBufs{b}, t, c, s, blockIdx.x, gridDim.x);
 }
 template <class T, class TC, int BK>
 __global__ void __launch_bounds__(NTH, 4) k_heff_y(Bufs b, const GemmTask* t, const GemmChunk* c, Sched s) {
-    gemm_body<T, TC, BK>(ArgBufs{b}, t, c, s, blockIdx.x, gridDim.x);
+    any_body<T, TC, BK>(ArgBufs{b}, t, c, s, blockIdx.x, gridDim.x);
 }
 
 // Grouped launch over several plans (independent solves advanced together):
@@ -789,9 +1066,9 @@ __device__ __forceinline__ void multi_body(const PlanDesc* __restrict__ plans, c
     sc.nwg = i32(so + offsetof(Sched, nwg));
     sc.nfull = i32(so + offsetof(Sched, nfull));
     sc.ntasks = i32(so + offsetof(Sched, ntasks));
-    gemm_body<T, TC, BK>(b, (const GemmTask*)u64(offsetof(PlanDesc, tasks)),
-                         (const GemmChunk*)u64(offsetof(PlanDesc, chunks)), sc, blockIdx.x - prefix[p],
-                         prefix[p + 1] - prefix[p]);
+    any_body<T, TC, BK>(b, (const GemmTask*)u64(offsetof(PlanDesc, tasks)),
+                        (const GemmChunk*)u64(offsetof(PlanDesc, chunks)), sc, blockIdx.x - prefix[p],
+                        prefix[p + 1] - prefix[p]);
 }
 template <class T, class TC, int BK>
 __global__ void __launch_bounds__(NTH, 4) k_multi_gemm(const PlanDesc* p, const int32_t* x, int n) {

@@ -84,7 +84,9 @@ static size_t size_class(size_t b) {
 }
 
 void* Engine::dalloc(size_t bytes) {
-    const size_t c = size_class(bytes);
+    // 64 bytes of slack past every block: the 16-byte reads of a GEMM
+    // operand's last elements never reach the end of an allocation
+    const size_t c = size_class(bytes + 64);
     // a cached block of this class, or of one of the next two classes
     auto it = cache_.lower_bound(c);
     if (it != cache_.end() && it->first <= c + c / 4) {
@@ -3408,6 +3410,7 @@ dmrg_status Engine::apply_static(const double* x, double* y, int prec) {
     off += al((size_t)std::max<int64_t>(zmax, 1) * es);
     const size_t p_off = off;
     off += al((size_t)slots * dmrgdev::kTileM * dmrgdev::kTileN * sizeof(double));
+    off += 256;   // slack past the last operand, as for allocated blocks
     if (off > cap) {
         std::ostringstream m;
         m << "this bond needs " << off << " bytes of static scratch; the array holds " << cap
