@@ -21,6 +21,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -184,8 +185,10 @@ def converge(name: str, prec: str, Ds, max_sweeps: int, budget_s: float, tol: fl
         out[D] = {"energy": energies[-1], "met": met}
         print(json.dumps({"mode": "converge", "workload": name, "precision": prec, "D": D,
                           "criterion_MeV": SWEEP_CRIT_MEV, "met": met, "sweeps": len(energies),
-                          "energy": energies[-1], "delta_E_MeV_last": deltas[-1],
-                          "delta_E_MeV": deltas, "s_per_sweep_mean": sum(walls) / len(walls),
+                          "energy": energies[-1],
+                          "delta_E_MeV_last": None if math.isnan(deltas[-1]) else deltas[-1],
+                          "delta_E_MeV": [None if math.isnan(x) else x for x in deltas],
+                          "s_per_sweep_mean": sum(walls) / len(walls),
                           "plateau_s": time.perf_counter() - t_plateau}), flush=True)
     ctx.close()
     pts = sorted((D, v["energy"]) for D, v in out.items() if v["met"])
@@ -375,14 +378,20 @@ def source_sha() -> str:
     return h.hexdigest()
 
 
-def measured_traffic(kernel):
+def measured_traffic(kernel, alg_bytes_per_launch):
     """HBM bytes per launch of `kernel` from its committed counter summary, or
-    None when there is none or the kernel source changed since it was taken."""
+    None when there is none, the kernel source changed since it was taken, or
+    it was taken over other launches (its algorithmic bytes per launch differ
+    from this run's by more than 0.1%: another schedule of sweeps)."""
     try:
-        kv = dict(l.strip().split("=", 1) for l in open(TRAFFIC_FILES[kernel]) if "=" in l and not l.startswith("#"))
+        lines = open(TRAFFIC_FILES[kernel]).read().splitlines()
     except (OSError, KeyError):
         return None
+    kv = dict(l.strip().split("=", 1) for l in lines if "=" in l and not l.startswith("#"))
     if kv.get("sources_sha256") != source_sha():
+        return None
+    alg = [float(l.split()[-1]) for l in lines if l.startswith("# algorithmic bytes per launch")]
+    if not alg or abs(alg[0] - alg_bytes_per_launch) > 1e-3 * alg_bytes_per_launch:
         return None
     return float(kv["hbm_bytes_per_launch"])
 
@@ -500,7 +509,7 @@ def summarize_counters(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, ben
     rl = b["roofline"]
     ph = rl if kernel == rl["kernel"] else rl.get("other_phase", {})
     if ph.get("kernel", rl["kernel"]) == kernel:
-        print(f"# algorithmic bytes per launch {ph['algorithmic_gb_per_launch'] * 1e9:.4g}")
+        print(f"# algorithmic bytes per launch {ph['algorithmic_gb_per_launch'] * 1e9:.7g}")
     print(f"fetch_bytes_per_launch={fetch:.6g}")
     print(f"write_bytes_per_launch={write:.6g}")
     print(f"hbm_bytes_per_launch={fetch + write:.6g}")
@@ -708,7 +717,7 @@ def main():
     kiss = t[f"{k}_issued_flops"] / nl
     ctype = {"fp64": "double, double, 16", "fp32": "float, float, 32"}.get(main_p, "")
     kname = f"{'k_heff_y' if k == 'gemm2' else 'k_heff_z'}<{ctype}>" if ctype else "k_gemm_bf16"
-    traffic = measured_traffic(kname)
+    traffic = measured_traffic(kname, t[f"{k}_bytes"] / nl)
     ko = "gemm1" if k == "gemm2" else "gemm2"   # the other H_eff phase, for reference
     nlo = max(t[f"{ko}_launches"], 1)
     oname = f"{'k_heff_y' if ko == 'gemm2' else 'k_heff_z'}<{ctype}>" if ctype else "k_gemm_bf16"
@@ -753,8 +762,9 @@ def main():
                            "heff_tflops": tt["heff_flops"] / max(tt["heff_seconds"], 1e-12) / 1e12,
                            "products_low": int(tt["products_low"]), "products_fp64": int(tt["products_fp64"]),
                            "heff_seconds": tt["heff_seconds"],
-                           "delta_E_MeV_timed": r["deltas"],
+                           "delta_E_MeV_timed": [None if math.isnan(x) else x for x in r["deltas"]],
                            "paper_sweep_criterion_met": bool(r["deltas"]) and abs(r["deltas"][-1]) < SWEEP_CRIT_MEV}
+        # (a NaN delta, the first sweep after the blocks were set up, compares False)
     if "fp64" in res and main_p != "fp64":
         e64, em = res["fp64"]["energy"], R["energy"]
         # sweep by sweep along the two trajectories (same schedule, same start)
