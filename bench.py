@@ -526,6 +526,30 @@ def copy_reference(mib):
     print(json.dumps({"copied_bytes": a.numel() * 4}))
 
 
+def hbm_check(mib: int, reps: int = 20):
+    """The roofline denominators checked on the device: the CU count and
+    clock the runtime reports, and the rate of a plain device-to-device copy
+    of `mib` MiB (read + write bytes over the event-timed copy)."""
+    import torch
+    p = torch.cuda.get_device_properties(0)
+    a = torch.ones(mib * (1 << 20) // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    s = e0.elapsed_time(e1) / 1e3 / reps
+    clk = getattr(p, "clock_rate", None)
+    print(json.dumps({"device": p.name, "gcn_arch": getattr(p, "gcnArchName", None),
+                      "compute_units": p.multi_processor_count, "clock_khz": clk,
+                      "copy_mib": mib, "copy_s": s, "copy_read_write_gb_s": 2 * a.numel() * 4 / s / 1e9}))
+
+
 def batched(k: int, precision: str = "fp32"):
     """Independent small solves: the first k seeded instances (p / sd / pf
     spaces, 2..8 particles per species, D from 64..512), one sweep each at
@@ -636,6 +660,8 @@ def main():
     ap.add_argument("--bench-json", help="the benchmark line of the profiled run")
     ap.add_argument("--kernel", help="kernel to summarise (default: the benchmark line's roofline kernel)")
     ap.add_argument("--copy-reference", type=int, metavar="MIB", help="one plain device copy of MIB MiB")
+    ap.add_argument("--hbm-check", type=int, metavar="MIB",
+                    help="CU count, clock and the rate of a timed device copy of MIB MiB")
     ap.add_argument("--plateaus", metavar="WORKLOAD",
                     help="energy vs discarded weight along --D-list plateaus (--per sweeps each)")
     ap.add_argument("--D-list", default="512,1024,2048")
@@ -662,6 +688,9 @@ def main():
         return
     if args.copy_reference:
         copy_reference(args.copy_reference)
+        return
+    if args.hbm_check:
+        hbm_check(args.hbm_check)
         return
     if args.batched:
         batched(args.batched)
